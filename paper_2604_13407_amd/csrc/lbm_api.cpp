@@ -1,0 +1,503 @@
+// Host side of liblbm.so: the C-ABI declared in include/pplbm.h.
+//
+// The handle keeps the caller's device pointers, a parameter block and the
+// index of the population array holding the current state.  All device work
+// is enqueued on the caller's stream; no device memory is allocated here.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pplbm.h"
+#include "lbm_internal.h"
+#include "lbm_node.h"
+
+using pplbm::RED_COUNT;
+using pplbm::StepParams;
+
+struct lbm_lattice {
+  lbm_config cfg;
+  lbm_buffers buf;
+  hipStream_t stream;
+  StepParams prm;
+  // user-facing parameters kept to rebuild prm
+  double s[9];
+  int scheme;
+  double eps, k1, k2;
+  int q2_policy;
+  double rho_s;
+  int cur = 0;  // 0: f_a holds the current state, 1: f_b
+  int64_t steps = 0;
+  bool initialized = false;
+  int seg_len = 64;
+  // workspace carve-up
+  double* partials = nullptr;
+  size_t max_parts = 0;
+  double* log = nullptr;
+  double* red_tmp = nullptr;
+  void* psi = nullptr;
+  std::string err;
+};
+
+namespace {
+
+std::string g_create_error;
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t elem_size(const lbm_config* c) { return c->precision == LBM_FP64 ? sizeof(double) : sizeof(float); }
+
+int fail(lbm_lattice* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+int hip_fail(lbm_lattice* h, hipError_t e, const char* what) {
+  return fail(h, LBM_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool config_ok(const lbm_config* c, std::string& why) {
+  if (!c) {
+    why = "config is NULL";
+    return false;
+  }
+  if (c->nx < 1 || c->ny < 1) {
+    why = "nx and ny must be >= 1";
+    return false;
+  }
+  if (9.0 * (double)c->nx * (double)c->ny >= 2147483647.0) {
+    why = "9*nx*ny must be < 2^31";
+    return false;
+  }
+  if (c->precision != LBM_FP64 && c->precision != LBM_FP32_DEV) {
+    why = "unknown precision";
+    return false;
+  }
+  if (c->kernel != LBM_KERNEL_FUSED && c->kernel != LBM_KERNEL_TWO_PASS) {
+    why = "unknown kernel";
+    return false;
+  }
+  if (!std::isfinite(c->rho_ref)) {
+    why = "rho_ref must be finite";
+    return false;
+  }
+  if (c->log_capacity < 1 || c->log_capacity > (1 << 24)) {
+    why = "log_capacity must be in [1, 2^24]";
+    return false;
+  }
+  return true;
+}
+
+constexpr int kMinSegLen = 16;
+
+int default_seg_len(int nx, int ny) {
+  int n_strips = (nx + 61) / 62;
+  long target = (long)ny * n_strips / 8192;  // aim for >= ~8k wavefronts
+  int s = (int)std::max<long>(kMinSegLen, std::min<long>(256, target));
+  return std::min(s, std::max(ny, 1));
+}
+
+size_t max_parts_for(const lbm_config* c) {
+  int n_strips, n_segs;
+  pplbm::fused_shape(c->nx, c->ny, kMinSegLen, &n_strips, &n_segs);
+  size_t fused = (size_t)n_strips * n_segs;
+  size_t two = (size_t)pplbm::two_pass_blocks(c->nx, c->ny);
+  return std::max(fused, two);
+}
+
+struct Layout {
+  size_t partials, log, red_tmp, psi, total;
+};
+
+Layout layout_for(const lbm_config* c) {
+  Layout L;
+  size_t off = 0;
+  L.partials = off;
+  off = align256(off + max_parts_for(c) * RED_COUNT * sizeof(double));
+  L.log = off;
+  off = align256(off + (size_t)c->log_capacity * RED_COUNT * sizeof(double));
+  L.red_tmp = off;
+  off = align256(off + RED_COUNT * sizeof(double));
+  L.psi = off;
+  off = align256(off + (size_t)c->nx * c->ny * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+void rebuild_params(lbm_lattice* h) {
+  StepParams& p = h->prm;
+  for (int k = 0; k < 9; ++k) {
+    p.s[k] = h->s[k];
+    p.h[k] = 1.0 - 0.5 * h->s[k];
+  }
+  double k1 = std::isnan(h->k1) ? -h->eps / 16.0 : h->k1;
+  double k2 = std::isnan(h->k2) ? -h->eps / 16.0 : h->k2;
+  p.q1 = 3.0 * (k1 + 2.0 * k2);
+  int q2 = h->q2_policy;
+  if (q2 == LBM_Q2_DEFAULT) q2 = (h->scheme == LBM_SCHEME_IMPROVED) ? LBM_Q2_NEG_HALF_Q1 : LBM_Q2_NEG_Q1;
+  p.q2 = (q2 == LBM_Q2_NEG_Q1) ? -1.0 : -0.5;
+  p.q7 = k1;
+  if (h->scheme == LBM_SCHEME_IMPROVED) {
+    p.qa = (30.0 * h->eps - 15.0) / 16.0;
+    p.qb = 3.0 * h->eps / 8.0;
+  } else {
+    p.qa = 0.0;
+    p.qb = 0.0;
+  }
+  double q = pplbm::psi_squared(p, h->rho_s);
+  p.psi_solid = std::sqrt(q > 0.0 ? q : 0.0);
+  p.gmag = std::sqrt(p.fx * p.fx + p.fy * p.fy);
+  p.ghx = p.gmag > 0 ? p.fx / p.gmag : 0.0;
+  p.ghy = p.gmag > 0 ? p.fy / p.gmag : 0.0;
+}
+
+bool all_finite(std::initializer_list<double> v) {
+  for (double d : v)
+    if (!std::isfinite(d)) return false;
+  return true;
+}
+
+void* state_ptr(lbm_lattice* h, int which) { return which == 0 ? h->buf.f_a : h->buf.f_b; }
+
+template <class T>
+hipError_t step_one(lbm_lattice* h, int reduce) {
+  pplbm::StepLaunch L;
+  L.f_in = state_ptr(h, h->cur);
+  L.f_out = state_ptr(h, 1 - h->cur);
+  L.mask = h->buf.mask;
+  L.wall_u = h->buf.wall_u;
+  L.psi = h->psi;
+  L.partials = h->partials;
+  L.kernel = h->cfg.kernel;
+  L.seg_len = h->seg_len;
+  L.reduce = reduce;
+  return pplbm::launch_step<T>(h->prm, L, h->stream);
+}
+
+int n_parts_of(lbm_lattice* h) {
+  if (h->cfg.kernel == LBM_KERNEL_TWO_PASS) return pplbm::two_pass_blocks(h->cfg.nx, h->cfg.ny);
+  int n_strips, n_segs;
+  pplbm::fused_shape(h->cfg.nx, h->cfg.ny, h->seg_len, &n_strips, &n_segs);
+  return n_strips * n_segs;
+}
+
+void fill_record(const double* v, int64_t step, lbm_reduction* r) {
+  r->mass = v[pplbm::RED_MASS];
+  r->mom_x = v[pplbm::RED_MOMX];
+  r->mom_y = v[pplbm::RED_MOMY];
+  r->wall_x = v[pplbm::RED_WALLX];
+  r->wall_y = v[pplbm::RED_WALLY];
+  r->uc_num = v[pplbm::RED_UC_NUM];
+  r->uc_den = v[pplbm::RED_UC_DEN];
+  r->buoy = v[pplbm::RED_BUOY];
+  r->pphi = v[pplbm::RED_PPHI];
+  r->faults = v[pplbm::RED_FAULTS];
+  r->step = step;
+}
+
+int fault_status(lbm_lattice* h, const lbm_reduction& r) {
+  if (r.faults > 0.0) {
+    char msg[160];
+    std::snprintf(msg, sizeof msg, "step %lld: %.0f node(s) with rho <= 0, negative psi^2 or non-finite values",
+                  (long long)r.step, r.faults);
+    return fail(h, std::isfinite(r.mass) ? LBM_ERR_EOS_DOMAIN : LBM_ERR_NONFINITE, msg);
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_abi_version(void) { return LBM_ABI_VERSION; }
+
+int lbm_state_bytes(const lbm_config* cfg, size_t* bytes) {
+  std::string why;
+  if (!bytes || !config_ok(cfg, why)) return LBM_ERR_INVALID_ARG;
+  *bytes = (size_t)9 * cfg->nx * cfg->ny * elem_size(cfg);
+  return LBM_OK;
+}
+
+int lbm_workspace_bytes(const lbm_config* cfg, size_t* bytes) {
+  std::string why;
+  if (!bytes || !config_ok(cfg, why)) return LBM_ERR_INVALID_ARG;
+  *bytes = layout_for(cfg).total;
+  return LBM_OK;
+}
+
+int lbm_create(const lbm_config* cfg, const lbm_buffers* buf, void* hip_stream, lbm_lattice** out) {
+  g_create_error.clear();
+  if (!out) {
+    g_create_error = "out is NULL";
+    return LBM_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  std::string why;
+  if (!config_ok(cfg, why)) {
+    g_create_error = why;
+    return LBM_ERR_INVALID_ARG;
+  }
+  if (!buf || !buf->f_a || !buf->f_b || !buf->workspace || buf->f_a == buf->f_b) {
+    g_create_error = "f_a, f_b and workspace must be distinct non-NULL device pointers";
+    return LBM_ERR_INVALID_ARG;
+  }
+  if (((uintptr_t)buf->workspace & 255u) != 0) {
+    g_create_error = "workspace must be 256-byte aligned";
+    return LBM_ERR_INVALID_ARG;
+  }
+  lbm_lattice* h = new (std::nothrow) lbm_lattice();
+  if (!h) {
+    g_create_error = "out of host memory";
+    return LBM_ERR_INVALID_ARG;
+  }
+  h->cfg = *cfg;
+  h->buf = *buf;
+  h->stream = (hipStream_t)hip_stream;
+  std::memset(&h->prm, 0, sizeof(h->prm));
+  h->prm.nx = cfg->nx;
+  h->prm.ny = cfg->ny;
+  h->prm.periodic_x = cfg->periodic_x ? 1 : 0;
+  h->prm.periodic_y = cfg->periodic_y ? 1 : 0;
+  h->prm.rho_ref = (cfg->precision == LBM_FP32_DEV) ? cfg->rho_ref : 0.0;
+  // defaults: Carnahan-Starling a = 1, b = 4, R = 1, T = 0.7 T_c
+  h->prm.eos_kind = LBM_EOS_CS;
+  h->prm.a = 1.0;
+  h->prm.b = 4.0;
+  h->prm.RT = 0.7 * 0.3773 / 4.0;
+  h->prm.k_eos = 1.0;
+  h->prm.G = -1.0;
+  h->prm.force_mode = LBM_FORCE_CONST;
+  h->prm.rho_g = 0.0;
+  h->prm.rho_l = 1.0;
+  for (int k = 0; k < 9; ++k) h->s[k] = 1.0;
+  h->scheme = LBM_SCHEME_IMPROVED;
+  h->eps = 0.0;
+  h->k1 = NAN;
+  h->k2 = NAN;
+  h->q2_policy = LBM_Q2_DEFAULT;
+  h->rho_s = 0.0;
+  h->seg_len = default_seg_len(cfg->nx, cfg->ny);
+  Layout L = layout_for(cfg);
+  char* ws = (char*)buf->workspace;
+  h->partials = (double*)(ws + L.partials);
+  h->max_parts = max_parts_for(cfg);
+  h->log = (double*)(ws + L.log);
+  h->red_tmp = (double*)(ws + L.red_tmp);
+  h->psi = (void*)(ws + L.psi);
+  rebuild_params(h);
+  *out = h;
+  return LBM_OK;
+}
+
+int lbm_destroy(lbm_lattice* h) {
+  delete h;
+  return LBM_OK;
+}
+
+const char* lbm_last_error(const lbm_lattice* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+int lbm_set_eos(lbm_lattice* h, int32_t kind, double a, double b, double R, double T, double k_eos) {
+  if (!h) return LBM_ERR_INVALID_ARG;
+  if (kind != LBM_EOS_VDW && kind != LBM_EOS_CS) return fail(h, LBM_ERR_INVALID_ARG, "unknown EOS kind");
+  if (!all_finite({a, b, R, T, k_eos}) || b <= 0 || R <= 0 || T <= 0 || k_eos <= 0 || a < 0)
+    return fail(h, LBM_ERR_INVALID_ARG, "EOS constants must be finite, b, R, T, k_eos > 0, a >= 0");
+  h->prm.eos_kind = kind;
+  h->prm.a = a;
+  h->prm.b = b;
+  h->prm.RT = R * T;
+  h->prm.k_eos = k_eos;
+  rebuild_params(h);
+  return LBM_OK;
+}
+
+int lbm_set_G(lbm_lattice* h, double G) {
+  if (!h) return LBM_ERR_INVALID_ARG;
+  if (!std::isfinite(G) || G == 0.0) return fail(h, LBM_ERR_INVALID_ARG, "G must be finite and non-zero");
+  h->prm.G = G;
+  rebuild_params(h);
+  return LBM_OK;
+}
+
+int lbm_set_relaxation(lbm_lattice* h, const double* s) {
+  if (!h) return LBM_ERR_INVALID_ARG;
+  if (!s) return fail(h, LBM_ERR_INVALID_ARG, "rates pointer is NULL");
+  for (int k = 0; k < 9; ++k)
+    if (!std::isfinite(s[k]) || s[k] < 0.0 || s[k] > 2.0)
+      return fail(h, LBM_ERR_INVALID_ARG, "every rate must be in [0, 2]");
+  for (int k = 0; k < 9; ++k) h->s[k] = s[k];
+  rebuild_params(h);
+  return LBM_OK;
+}
+
+int lbm_set_scheme(lbm_lattice* h, int32_t scheme, double eps, double k1, double k2, int32_t q2_policy) {
+  if (!h) return LBM_ERR_INVALID_ARG;
+  if (scheme != LBM_SCHEME_ORIGINAL && scheme != LBM_SCHEME_IMPROVED)
+    return fail(h, LBM_ERR_INVALID_ARG, "unknown scheme");
+  if (q2_policy < LBM_Q2_DEFAULT || q2_policy > LBM_Q2_NEG_HALF_Q1)
+    return fail(h, LBM_ERR_INVALID_ARG, "unknown q2 policy");
+  if (!std::isfinite(eps) || (!std::isnan(k1) && !std::isfinite(k1)) || (!std::isnan(k2) && !std::isfinite(k2)))
+    return fail(h, LBM_ERR_INVALID_ARG, "eps, k1, k2 must be finite (k1, k2 may be NaN)");
+  h->scheme = scheme;
+  h->eps = eps;
+  h->k1 = k1;
+  h->k2 = k2;
+  h->q2_policy = q2_policy;
+  rebuild_params(h);
+  return LBM_OK;
+}
+
+int lbm_set_body_force(lbm_lattice* h, int32_t mode, double fx, double fy) {
+  if (!h) return LBM_ERR_INVALID_ARG;
+  if (mode != LBM_FORCE_CONST && mode != LBM_FORCE_BUOYANT) return fail(h, LBM_ERR_INVALID_ARG, "unknown force mode");
+  if (!all_finite({fx, fy})) return fail(h, LBM_ERR_INVALID_ARG, "force must be finite");
+  h->prm.force_mode = mode;
+  h->prm.fx = fx;
+  h->prm.fy = fy;
+  rebuild_params(h);
+  return LBM_OK;
+}
+
+int lbm_set_phase_densities(lbm_lattice* h, double rho_g, double rho_l) {
+  if (!h) return LBM_ERR_INVALID_ARG;
+  if (!all_finite({rho_g, rho_l}) || !(rho_g > 0.0) || !(rho_l > rho_g))
+    return fail(h, LBM_ERR_INVALID_ARG, "need 0 < rho_g < rho_l");
+  h->prm.rho_g = rho_g;
+  h->prm.rho_l = rho_l;
+  rebuild_params(h);
+  return LBM_OK;
+}
+
+int lbm_set_walls(lbm_lattice* h, double rho_s) {
+  if (!h) return LBM_ERR_INVALID_ARG;
+  if (!std::isfinite(rho_s) || rho_s < 0.0) return fail(h, LBM_ERR_INVALID_ARG, "rho_s must be finite and >= 0");
+  h->rho_s = rho_s;
+  rebuild_params(h);
+  return LBM_OK;
+}
+
+int lbm_init_equilibrium(lbm_lattice* h, const double* rho0, const double* ux0, const double* uy0) {
+  if (!h) return LBM_ERR_INVALID_ARG;
+  if (!rho0) return fail(h, LBM_ERR_INVALID_ARG, "rho0 is NULL");
+  hipError_t e = (h->cfg.precision == LBM_FP64)
+                     ? pplbm::launch_init<double>(h->prm, rho0, ux0, uy0, h->buf.f_a, h->buf.f_b, h->stream)
+                     : pplbm::launch_init<float>(h->prm, rho0, ux0, uy0, h->buf.f_a, h->buf.f_b, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "init launch");
+  h->cur = 0;
+  h->steps = 0;
+  h->initialized = true;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_lattice* h, int64_t n, int32_t reduce_every, lbm_reduction* out, int64_t n_out) {
+  if (!h) return LBM_ERR_INVALID_ARG;
+  if (!h->initialized) return fail(h, LBM_ERR_STATE, "lbm_step before lbm_init_equilibrium / lbm_set_state");
+  if (n < 0 || reduce_every < 0 || n_out < 0) return fail(h, LBM_ERR_INVALID_ARG, "negative count");
+  int64_t records = 0;
+  if (reduce_every > 0) records = (h->steps + n) / reduce_every - h->steps / reduce_every;
+  if (records > h->cfg.log_capacity)
+    return fail(h, LBM_ERR_INVALID_ARG, "more reduction records than log_capacity in one call");
+  std::vector<int64_t> rec_steps;
+  rec_steps.reserve((size_t)records);
+  const int parts = n_parts_of(h);
+  for (int64_t t = 0; t < n; ++t) {
+    int64_t idx = h->steps + 1;
+    int reduce = (reduce_every > 0 && idx % reduce_every == 0) ? 1 : 0;
+    hipError_t e = (h->cfg.precision == LBM_FP64) ? step_one<double>(h, reduce) : step_one<float>(h, reduce);
+    if (e != hipSuccess) return hip_fail(h, e, "step launch");
+    if (reduce) {
+      e = pplbm::launch_finalize(h->partials, parts, h->log + rec_steps.size() * RED_COUNT, h->stream);
+      if (e != hipSuccess) return hip_fail(h, e, "reduction launch");
+      rec_steps.push_back(idx);
+    }
+    h->cur = 1 - h->cur;
+    h->steps = idx;
+  }
+  if (out && !rec_steps.empty() && n_out > 0) {
+    size_t ncopy = (size_t)std::min<int64_t>(n_out, (int64_t)rec_steps.size());
+    std::vector<double> host(ncopy * RED_COUNT);
+    hipError_t e = hipMemcpyAsync(host.data(), h->log, host.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "reduction copy");
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "stream synchronize");
+    int status = LBM_OK;
+    for (size_t r = 0; r < ncopy; ++r) {
+      fill_record(&host[r * RED_COUNT], rec_steps[r], &out[r]);
+      if (status == LBM_OK) status = fault_status(h, out[r]);
+    }
+    return status;
+  }
+  return LBM_OK;
+}
+
+int lbm_step_count(const lbm_lattice* h, int64_t* steps) {
+  if (!h || !steps) return LBM_ERR_INVALID_ARG;
+  *steps = h->steps;
+  return LBM_OK;
+}
+
+int lbm_read_fields(lbm_lattice* h, double* rho, double* ux, double* uy, double* fx, double* fy, double* psi) {
+  if (!h) return LBM_ERR_INVALID_ARG;
+  if (!h->initialized) return fail(h, LBM_ERR_STATE, "read before init");
+  const void* f = state_ptr(h, h->cur);
+  hipError_t e = (h->cfg.precision == LBM_FP64)
+                     ? pplbm::launch_fields<double>(h->prm, f, h->buf.mask, h->buf.wall_u, h->psi, rho, ux, uy, fx,
+                                                    fy, psi, h->partials, 0, h->stream)
+                     : pplbm::launch_fields<float>(h->prm, f, h->buf.mask, h->buf.wall_u, h->psi, rho, ux, uy, fx, fy,
+                                                   psi, h->partials, 0, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "fields launch");
+  return LBM_OK;
+}
+
+int lbm_reduce(lbm_lattice* h, lbm_reduction* out) {
+  if (!h || !out) return LBM_ERR_INVALID_ARG;
+  if (!h->initialized) return fail(h, LBM_ERR_STATE, "reduce before init");
+  const void* f = state_ptr(h, h->cur);
+  hipError_t e = (h->cfg.precision == LBM_FP64)
+                     ? pplbm::launch_fields<double>(h->prm, f, h->buf.mask, h->buf.wall_u, h->psi, nullptr, nullptr,
+                                                    nullptr, nullptr, nullptr, nullptr, h->partials, 1, h->stream)
+                     : pplbm::launch_fields<float>(h->prm, f, h->buf.mask, h->buf.wall_u, h->psi, nullptr, nullptr,
+                                                   nullptr, nullptr, nullptr, nullptr, h->partials, 1, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "fields launch");
+  e = pplbm::launch_finalize(h->partials, pplbm::two_pass_blocks(h->cfg.nx, h->cfg.ny), h->red_tmp, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "reduction launch");
+  double host[RED_COUNT];
+  e = hipMemcpyAsync(host, h->red_tmp, sizeof host, hipMemcpyDeviceToHost, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "reduction copy");
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "stream synchronize");
+  fill_record(host, h->steps + 1, out);
+  return fault_status(h, *out);
+}
+
+int lbm_state_ptr(const lbm_lattice* h, void** f) {
+  if (!h || !f) return LBM_ERR_INVALID_ARG;
+  *f = h->cur == 0 ? h->buf.f_a : h->buf.f_b;
+  return LBM_OK;
+}
+
+int lbm_get_state(lbm_lattice* h, void* dst) {
+  if (!h || !dst) return LBM_ERR_INVALID_ARG;
+  if (!h->initialized) return fail(h, LBM_ERR_STATE, "get_state before init");
+  size_t bytes = (size_t)9 * h->cfg.nx * h->cfg.ny * elem_size(&h->cfg);
+  hipError_t e = hipMemcpyAsync(dst, state_ptr(h, h->cur), bytes, hipMemcpyDeviceToDevice, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "state copy");
+  return LBM_OK;
+}
+
+int lbm_set_state(lbm_lattice* h, const void* src, int64_t step) {
+  if (!h || !src || step < 0) return LBM_ERR_INVALID_ARG;
+  size_t bytes = (size_t)9 * h->cfg.nx * h->cfg.ny * elem_size(&h->cfg);
+  hipError_t e = hipMemcpyAsync(h->buf.f_a, src, bytes, hipMemcpyDeviceToDevice, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "state copy");
+  e = hipMemcpyAsync(h->buf.f_b, src, bytes, hipMemcpyDeviceToDevice, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "state copy");
+  h->cur = 0;
+  h->steps = step;
+  h->initialized = true;
+  return LBM_OK;
+}
+
+}  // extern "C"

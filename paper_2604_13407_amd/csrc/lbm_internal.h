@@ -1,0 +1,37 @@
+// Launch interface between the C-ABI host code and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_params.h"
+
+namespace pplbm {
+
+struct StepLaunch {
+  const void* f_in;
+  void* f_out;
+  const uint8_t* mask;
+  const double* wall_u;
+  void* psi;          // two-pass pseudopotential field (double)
+  double* partials;   // per-block / per-wave reduction partials
+  int kernel;         // 0 fused, 1 two-pass
+  int seg_len;        // fused: rows per wavefront
+  int reduce;         // 1: write reduction partials this step
+};
+
+int two_pass_blocks(int nx, int ny);
+void fused_shape(int nx, int ny, int seg_len, int* n_strips, int* n_segs);
+
+template <class S>
+hipError_t launch_init(const StepParams& p, const double* rho0, const double* ux0, const double* uy0, void* fa,
+                       void* fb, hipStream_t s);
+template <class S>
+hipError_t launch_step(const StepParams& p, const StepLaunch& L, hipStream_t s);
+template <class S>
+hipError_t launch_fields(const StepParams& p, const void* f, const uint8_t* mask, const double* wall_u, void* psi,
+                         double* rho, double* ux, double* uy, double* fx, double* fy, double* psi_o,
+                         double* partials, int reduce, hipStream_t s);
+hipError_t launch_finalize(const double* partials, int n_parts, double* out, hipStream_t s);
+
+}  // namespace pplbm

@@ -1,0 +1,264 @@
+"""Python binding of liblbm.so (the C-ABI in include/pplbm.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  PyTorch provides the device memory (the population arrays, the
+workspace, masks and outputs) and the stream; the library receives raw
+pointers and the stream handle.  There is no CPU fallback: without the built
+library or a GPU, constructing a Lattice raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Dict, List, Optional
+
+import numpy as np
+import torch
+
+from . import build as _build
+
+LBM_OK = 0
+ERRORS = {-1: "LBM_ERR_INVALID_ARG", -2: "LBM_ERR_HIP", -3: "LBM_ERR_NONFINITE", -4: "LBM_ERR_EOS_DOMAIN",
+          -5: "LBM_ERR_UNSUPPORTED", -6: "LBM_ERR_STATE"}
+FP64, FP32_DEV = 0, 1
+KERNEL_FUSED, KERNEL_TWO_PASS = 0, 1
+EOS_VDW, EOS_CS = 0, 1
+SCHEME_ORIGINAL, SCHEME_IMPROVED = 0, 1
+Q2_DEFAULT, Q2_NEG_Q1, Q2_NEG_HALF_Q1 = 0, 1, 2
+FORCE_CONST, FORCE_BUOYANT = 0, 1
+
+RED_FIELDS = ("mass", "mom_x", "mom_y", "wall_x", "wall_y", "uc_num", "uc_den", "buoy", "pphi", "faults")
+
+# Every symbol include/pplbm.h declares.
+EXPORTS = ("lbm_abi_version", "lbm_state_bytes", "lbm_workspace_bytes", "lbm_create", "lbm_destroy",
+           "lbm_last_error", "lbm_set_eos", "lbm_set_G", "lbm_set_relaxation", "lbm_set_scheme",
+           "lbm_set_body_force", "lbm_set_phase_densities", "lbm_set_walls", "lbm_init_equilibrium", "lbm_step",
+           "lbm_step_count", "lbm_read_fields", "lbm_reduce", "lbm_state_ptr", "lbm_get_state", "lbm_set_state")
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("periodic_x", C.c_int32), ("periodic_y", C.c_int32),
+                ("precision", C.c_int32), ("kernel", C.c_int32), ("rho_ref", C.c_double),
+                ("log_capacity", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Buffers(C.Structure):
+    _fields_ = [("f_a", C.c_void_p), ("f_b", C.c_void_p), ("workspace", C.c_void_p), ("mask", C.c_void_p),
+                ("wall_u", C.c_void_p)]
+
+
+class Reduction(C.Structure):
+    _fields_ = [(n, C.c_double) for n in RED_FIELDS] + [("step", C.c_int64)]
+
+    def as_dict(self) -> Dict[str, float]:
+        d = {n: getattr(self, n) for n in RED_FIELDS}
+        d["step"] = int(self.step)
+        return d
+
+
+_lib = None
+
+
+def lib():
+    """Loads liblbm.so (building it first only if it does not exist)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        vp, dp = C.c_void_p, C.POINTER(C.c_double)
+        L.lbm_abi_version.restype = C.c_int
+        L.lbm_state_bytes.argtypes = [C.POINTER(Config), C.POINTER(C.c_size_t)]
+        L.lbm_workspace_bytes.argtypes = [C.POINTER(Config), C.POINTER(C.c_size_t)]
+        L.lbm_create.argtypes = [C.POINTER(Config), C.POINTER(Buffers), vp, C.POINTER(vp)]
+        L.lbm_destroy.argtypes = [vp]
+        L.lbm_last_error.argtypes = [vp]
+        L.lbm_last_error.restype = C.c_char_p
+        L.lbm_set_eos.argtypes = [vp, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.lbm_set_G.argtypes = [vp, C.c_double]
+        L.lbm_set_relaxation.argtypes = [vp, dp]
+        L.lbm_set_scheme.argtypes = [vp, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_int32]
+        L.lbm_set_body_force.argtypes = [vp, C.c_int32, C.c_double, C.c_double]
+        L.lbm_set_phase_densities.argtypes = [vp, C.c_double, C.c_double]
+        L.lbm_set_walls.argtypes = [vp, C.c_double]
+        L.lbm_init_equilibrium.argtypes = [vp, vp, vp, vp]
+        L.lbm_step.argtypes = [vp, C.c_int64, C.c_int32, C.POINTER(Reduction), C.c_int64]
+        L.lbm_step_count.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.lbm_read_fields.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.lbm_reduce.argtypes = [vp, C.POINTER(Reduction)]
+        L.lbm_state_ptr.argtypes = [vp, C.POINTER(vp)]
+        L.lbm_get_state.argtypes = [vp, vp]
+        L.lbm_set_state.argtypes = [vp, vp, C.c_int64]
+        _lib = L
+    return _lib
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev(a, device, dtype) -> Optional[torch.Tensor]:
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        a = torch.from_numpy(np.ascontiguousarray(a))
+    return a.to(device=device, dtype=dtype).contiguous()
+
+
+class Lattice:
+    """One lattice on one GPU.  All device memory is owned by torch tensors held here."""
+
+    def __init__(self, nx: int, ny: int, periodic_x: bool = True, periodic_y: bool = True,
+                 precision: int = FP64, kernel: int = KERNEL_FUSED, rho_ref: float = 0.0, mask=None, wall_u=None,
+                 device: str = "cuda:0", log_capacity: int = 4096, stream: Optional[torch.cuda.Stream] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("liblbm needs a GPU: torch.cuda.is_available() is False")
+        self.device = torch.device(device)
+        self.nx, self.ny = nx, ny
+        self.precision = precision
+        self.cfg = Config(nx, ny, int(periodic_x), int(periodic_y), precision, kernel, float(rho_ref),
+                          int(log_capacity), 0)
+        L = lib()
+        sb, wb = C.c_size_t(0), C.c_size_t(0)
+        self._check(L.lbm_state_bytes(C.byref(self.cfg), C.byref(sb)), None)
+        self._check(L.lbm_workspace_bytes(C.byref(self.cfg), C.byref(wb)), None)
+        self.dtype = torch.float64 if precision == FP64 else torch.float32
+        self.f_a = torch.empty((9, ny, nx), dtype=self.dtype, device=self.device)
+        self.f_b = torch.empty((9, ny, nx), dtype=self.dtype, device=self.device)
+        assert self.f_a.numel() * self.f_a.element_size() == sb.value
+        # torch's caching allocator returns >= 512-byte aligned blocks
+        self.workspace = torch.empty(wb.value, dtype=torch.uint8, device=self.device)
+        self.mask = _dev(mask, self.device, torch.uint8)
+        self.wall_u = _dev(wall_u, self.device, torch.float64)
+        if self.mask is not None:
+            assert tuple(self.mask.shape) == (ny, nx)
+        if self.wall_u is not None:
+            assert tuple(self.wall_u.shape) == (2, ny, nx)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.buf = Buffers(self.f_a.data_ptr(), self.f_b.data_ptr(), self.workspace.data_ptr(),
+                           None if self.mask is None else self.mask.data_ptr(),
+                           None if self.wall_u is None else self.wall_u.data_ptr())
+        h = C.c_void_p(0)
+        with torch.cuda.device(self.device):
+            rc = L.lbm_create(C.byref(self.cfg), C.byref(self.buf), C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != LBM_OK:
+            raise LbmError(rc, L.lbm_last_error(None).decode())
+        self.h = h
+
+    # ------------------------------------------------------------ plumbing
+    def _check(self, rc: int, h):
+        if rc != LBM_OK:
+            raise LbmError(rc, lib().lbm_last_error(h).decode())
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and _lib is not None:
+            _lib.lbm_destroy(h)
+            self.h = None
+
+    # ------------------------------------------------------------ parameters
+    def set_eos(self, kind: int, a: float, b: float, R: float, T: float, k_eos: float = 1.0):
+        self._check(lib().lbm_set_eos(self.h, kind, a, b, R, T, k_eos), self.h)
+
+    def set_G(self, G: float):
+        self._check(lib().lbm_set_G(self.h, G), self.h)
+
+    def set_relaxation(self, s):
+        arr = (C.c_double * 9)(*[float(v) for v in s])
+        self._check(lib().lbm_set_relaxation(self.h, arr), self.h)
+
+    def set_scheme(self, scheme: int, eps: float, k1: Optional[float] = None, k2: Optional[float] = None,
+                   q2_policy: int = Q2_DEFAULT):
+        k1 = math.nan if k1 is None else k1
+        k2 = math.nan if k2 is None else k2
+        self._check(lib().lbm_set_scheme(self.h, scheme, eps, k1, k2, q2_policy), self.h)
+
+    def set_body_force(self, mode: int, fx: float, fy: float):
+        self._check(lib().lbm_set_body_force(self.h, mode, fx, fy), self.h)
+
+    def set_phase_densities(self, rho_g: float, rho_l: float):
+        self._check(lib().lbm_set_phase_densities(self.h, rho_g, rho_l), self.h)
+
+    def set_walls(self, rho_s: float):
+        self._check(lib().lbm_set_walls(self.h, rho_s), self.h)
+
+    # ------------------------------------------------------------ state
+    def init_equilibrium(self, rho0, ux0=None, uy0=None):
+        r = _dev(rho0, self.device, torch.float64)
+        u = _dev(ux0, self.device, torch.float64)
+        v = _dev(uy0, self.device, torch.float64)
+        assert tuple(r.shape) == (self.ny, self.nx)
+        self._keep = (r, u, v)  # alive until the enqueued kernel has read them
+        self._check(lib().lbm_init_equilibrium(self.h, _ptr(r), _ptr(u), _ptr(v)), self.h)
+
+    def step(self, n: int, reduce_every: int = 0) -> List[Dict[str, float]]:
+        if reduce_every > 0:
+            cnt = self.step_count
+            nrec = (cnt + n) // reduce_every - cnt // reduce_every
+            out = (Reduction * max(nrec, 1))()
+            self._check(lib().lbm_step(self.h, n, reduce_every, out, nrec), self.h)
+            return [out[i].as_dict() for i in range(nrec)]
+        self._check(lib().lbm_step(self.h, n, 0, None, 0), self.h)
+        return []
+
+    @property
+    def step_count(self) -> int:
+        v = C.c_int64(0)
+        self._check(lib().lbm_step_count(self.h, C.byref(v)), self.h)
+        return v.value
+
+    def state(self) -> torch.Tensor:
+        """The population array that holds the current state (deviations in FP32_DEV)."""
+        p = C.c_void_p(0)
+        self._check(lib().lbm_state_ptr(self.h, C.byref(p)), self.h)
+        return self.f_a if p.value == self.f_a.data_ptr() else self.f_b
+
+    def get_state(self) -> torch.Tensor:
+        dst = torch.empty_like(self.f_a)
+        self._check(lib().lbm_get_state(self.h, _ptr(dst)), self.h)
+        return dst
+
+    def set_state(self, src: torch.Tensor, step: int = 0):
+        src = src.to(device=self.device, dtype=self.dtype).contiguous()
+        self._keep = (src,)
+        self._check(lib().lbm_set_state(self.h, _ptr(src), step), self.h)
+
+    def read_fields(self) -> Dict[str, torch.Tensor]:
+        """Pre-collision fields of the current state: rho, ux, uy, fintx, finty, psi (FP64, device)."""
+        out = {k: torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+               for k in ("rho", "ux", "uy", "fintx", "finty", "psi")}
+        self._check(lib().lbm_read_fields(self.h, _ptr(out["rho"]), _ptr(out["ux"]), _ptr(out["uy"]),
+                                          _ptr(out["fintx"]), _ptr(out["finty"]), _ptr(out["psi"])), self.h)
+        return out
+
+    def reduce(self) -> Dict[str, float]:
+        r = Reduction()
+        self._check(lib().lbm_reduce(self.h, C.byref(r)), self.h)
+        return r.as_dict()
+
+    # ------------------------------------------------------------ convenience
+    @classmethod
+    def from_workload(cls, w, precision: int = FP64, kernel: int = KERNEL_FUSED, rho_ref: Optional[float] = None,
+                      device: str = "cuda:0", init: bool = True, **kw) -> "Lattice":
+        """A lattice with the parameters and seeded inputs of a workloads.Workload."""
+        if rho_ref is None:
+            rho_ref = w.rho_g if precision == FP32_DEV else 0.0
+        lat = cls(w.nx, w.ny, w.periodic_x, w.periodic_y, precision, kernel, rho_ref, mask=w.mask(),
+                  wall_u=w.wall_velocity(), device=device, **kw)
+        lat.set_eos(w.eos_kind, w.a, w.b, w.R, w.T, w.k_eos)
+        lat.set_G(w.G)
+        lat.set_relaxation(w.s)
+        lat.set_scheme(w.scheme, w.eps, w.k1, w.k2)
+        lat.set_body_force(w.force_mode, w.fx, w.fy)
+        lat.set_phase_densities(w.rho_g, w.rho_l)
+        lat.set_walls(w.rho_s)
+        if init:
+            lat.init_equilibrium(w.rho0())
+        return lat

@@ -1,0 +1,106 @@
+"""Host-side checks of the C-ABI library: it loads, exports every symbol the
+header declares, and validates arguments without touching a GPU."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+from paper_2604_13407_amd import lattice as LT
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "pplbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[A-Za-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = LT.lib()
+    names = declared_symbols()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(LT.EXPORTS)
+    assert L.lbm_abi_version() == 1
+
+
+def cfg(**kw):
+    base = dict(nx=64, ny=32, periodic_x=1, periodic_y=0, precision=LT.FP32_DEV, kernel=LT.KERNEL_FUSED,
+                rho_ref=0.1, log_capacity=16, reserved=0)
+    base.update(kw)
+    return LT.Config(**base)
+
+
+def test_sizes_and_config_validation():
+    L = LT.lib()
+    b = C.c_size_t(0)
+    assert L.lbm_state_bytes(C.byref(cfg()), C.byref(b)) == 0 and b.value == 9 * 64 * 32 * 4
+    assert L.lbm_state_bytes(C.byref(cfg(precision=LT.FP64)), C.byref(b)) == 0 and b.value == 9 * 64 * 32 * 8
+    assert L.lbm_workspace_bytes(C.byref(cfg()), C.byref(b)) == 0 and b.value % 256 == 0 and b.value > 64 * 32 * 4
+    for bad in (dict(nx=0), dict(ny=-3), dict(precision=7), dict(kernel=5), dict(log_capacity=0),
+                dict(nx=100000, ny=100000), dict(rho_ref=math.inf)):
+        assert L.lbm_state_bytes(C.byref(cfg(**bad)), C.byref(b)) == -1, bad
+
+
+def fake_handle():
+    """A handle around fake pointers: valid for host-only calls, never for launches."""
+    L = LT.lib()
+    c = cfg()
+    buf = LT.Buffers(0x10000, 0x20000, 0x30000, None, None)
+    h = C.c_void_p(0)
+    assert L.lbm_create(C.byref(c), C.byref(buf), None, C.byref(h)) == 0
+    return L, h
+
+
+def test_create_rejects_bad_buffers():
+    L = LT.lib()
+    h = C.c_void_p(0)
+    for buf in (LT.Buffers(0, 0x2000, 0x3000, None, None), LT.Buffers(0x1000, 0x1000, 0x3000, None, None),
+                LT.Buffers(0x1000, 0x2000, 0x3001, None, None)):
+        assert L.lbm_create(C.byref(cfg()), C.byref(buf), None, C.byref(h)) == -1
+        assert L.lbm_last_error(None)
+    assert L.lbm_create(C.byref(cfg(nx=0)), C.byref(LT.Buffers(0x1000, 0x2000, 0x3000, None, None)), None,
+                        C.byref(h)) == -1
+
+
+def test_setters_validate_and_state_errors_without_a_gpu():
+    L, h = fake_handle()
+    try:
+        assert L.lbm_set_eos(h, 3, 1, 4, 1, 0.07, 1) == -1
+        assert L.lbm_set_eos(h, 1, 1, -4, 1, 0.07, 1) == -1
+        assert L.lbm_set_eos(h, 1, 1, 4, 1, 0.07, 1) == 0
+        assert L.lbm_set_G(h, 0.0) == -1 and L.lbm_set_G(h, math.nan) == -1 and L.lbm_set_G(h, -1.0) == 0
+        good = (C.c_double * 9)(1, 1.25, 1.25, 1, 1.2, 1, 1.2, 1.25, 1.25)
+        bad = (C.c_double * 9)(1, 2.5, 1.25, 1, 1.2, 1, 1.2, 1.25, 1.25)
+        assert L.lbm_set_relaxation(h, good) == 0 and L.lbm_set_relaxation(h, bad) == -1
+        assert L.lbm_set_scheme(h, 2, 1.0, math.nan, math.nan, 0) == -1
+        assert L.lbm_set_scheme(h, 1, 1.0, math.nan, math.nan, 9) == -1
+        assert L.lbm_set_scheme(h, 1, math.inf, math.nan, math.nan, 0) == -1
+        assert L.lbm_set_scheme(h, 0, 1.895, math.nan, math.nan, 0) == 0
+        assert L.lbm_set_body_force(h, 3, 0, 0) == -1 and L.lbm_set_body_force(h, 1, 0, -1e-7) == 0
+        assert L.lbm_set_phase_densities(h, 0.3, 0.1) == -1 and L.lbm_set_phase_densities(h, 0.01, 0.3) == 0
+        assert L.lbm_set_walls(h, -1.0) == -1 and L.lbm_set_walls(h, 0.01) == 0
+        # stepping or reading before initialisation is a state error (checked before any launch)
+        assert L.lbm_step(h, 1, 0, None, 0) == -6
+        assert L.lbm_read_fields(h, None, None, None, None, None, None) == -6
+        r = LT.Reduction()
+        assert L.lbm_reduce(h, C.byref(r)) == -6
+        assert L.lbm_get_state(h, C.c_void_p(0x5000)) == -6
+        assert L.lbm_init_equilibrium(h, None, None, None) == -1
+        assert "NULL" in L.lbm_last_error(h).decode()
+        n = C.c_int64(-1)
+        assert L.lbm_step_count(h, C.byref(n)) == 0 and n.value == 0
+    finally:
+        L.lbm_destroy(h)
+
+
+def test_no_cpu_fallback_without_a_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(RuntimeError):
+        LT.Lattice(8, 8)

@@ -1,0 +1,122 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark times (fused kernel, default rows per wavefront).
+
+* A few steps of the whole lattice against the whole-lattice oracle.
+* Longer runs checked on sampled windows: after k steps a node depends only on
+  the initial state within 2k nodes (one node by streaming and one more
+  through the pseudopotential stencil), so the oracle run on a crop with a
+  margin of 2k + 2 reproduces the full lattice exactly in the crop's interior.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2604_13407_amd import lattice as LT
+from paper_2604_13407_amd import workloads as WL
+from tests.helpers import oracle_params
+
+pytestmark = pytest.mark.gpu
+
+
+def run_gpu(w, steps, precision):
+    print(f"[fullsize] gpu {w.name} {w.nx}x{w.ny} steps={steps} precision={precision}", flush=True)
+    lat = LT.Lattice.from_workload(w, precision=precision)
+    lat.step(steps)
+    d = lat.read_fields()
+    torch.cuda.synchronize()
+    return lat, {k: v.cpu().numpy() for k, v in d.items()}
+
+
+def axis_crop(a0, a1, n, periodic, m):
+    """Indices of the crop along one axis, whether the crop is periodic, and the
+    window's offset in it.  Non-periodic axes keep their real walls; the other
+    crop edges are placeholders (periodic or walls) too far away to matter."""
+    c0, c1 = a0 - m, a1 + m
+    if c1 - c0 >= n:
+        return np.arange(n), periodic, a0
+    if periodic:
+        return np.arange(c0, c1) % n, True, a0 - c0
+    c0, c1 = max(c0, 0), min(c1, n)
+    return np.arange(c0, c1), False, a0 - c0
+
+
+def crop_oracle(w, steps, x0, x1, y0, y1):
+    """Oracle on the window [x0, x1) x [y0, y1) grown by a light-cone margin;
+    returns the window's fields after `steps` steps."""
+    m = 2 * steps + 2
+    xs, px, sx = axis_crop(x0, x1, w.nx, w.periodic_x, m)
+    ys, py, sy = axis_crop(y0, y1, w.ny, w.periodic_y, m)
+    rho0 = np.ascontiguousarray(w.rho0()[np.ix_(ys, xs)])
+    mask = w.mask()
+    mask = None if mask is None else np.ascontiguousarray(mask[np.ix_(ys, xs)])
+    wu = w.wall_velocity()
+    wu = None if wu is None else np.ascontiguousarray(wu[:, ys][:, :, xs])
+    p = oracle_params(w, nx=len(xs), ny=len(ys), periodic_x=px, periodic_y=py)
+    o = O.Oracle(p, mask=mask, wall_u=wu).init(rho0)
+    o.step(steps)
+    mac = o.macros()
+    return {k: mac[k][sy:sy + (y1 - y0), sx:sx + (x1 - x0)] for k in ("rho", "ux", "uy", "fintx", "finty", "psi")}
+
+
+def check(w, g, o, x0, x1, y0, y1, precision, scale_u):
+    mask = w.mask()
+    fl = np.ones((y1 - y0, x1 - x0), bool) if mask is None else (mask[y0:y1, x0:x1] == 0)
+    gw = {k: g[k][y0:y1, x0:x1] for k in o}
+    if precision == LT.FP64:
+        for k in ("rho", "ux", "uy", "psi"):
+            sc = scale_u if k in ("ux", "uy") else np.max(np.abs(o[k][fl]))
+            err = np.max(np.abs(gw[k][fl] - o[k][fl])) / sc
+            assert err <= 1e-12, (w.name, k, err)
+    else:
+        rerr = np.max(np.abs(gw["rho"][fl] - o["rho"][fl]) / o["rho"][fl])
+        uerr = max(np.max(np.abs(gw["ux"][fl] - o["ux"][fl])), np.max(np.abs(gw["uy"][fl] - o["uy"][fl]))) / scale_u
+        assert rerr <= 1e-5, (w.name, "rho", rerr)
+        assert uerr <= 1e-4, (w.name, "u", uerr)
+
+
+@pytest.mark.parametrize("precision", [LT.FP32_DEV, LT.FP64])
+def test_droplet_full_lattice_few_steps(precision):
+    # 2048 x 16384 droplet channel, whole lattice against the whole-lattice oracle
+    w = WL.droplet()
+    steps = 2
+    lat, g = run_gpu(w, steps, precision)
+    print("[fullsize] oracle droplet full lattice", flush=True)
+    o = O.Oracle(oracle_params(w)).init(w.rho0())
+    red = o.step(steps, reductions=True)
+    om = o.macros()
+    scale_u = max(np.max(np.abs(om["ux"])), np.max(np.abs(om["uy"])))
+    check(w, g, {k: om[k] for k in ("rho", "ux", "uy", "fintx", "finty", "psi")}, 0, w.nx, 0, w.ny, precision,
+          scale_u)
+    rec = lat.reduce()
+    mass_ref = om["red"]["mass"]
+    assert rec["mass"] == pytest.approx(mass_ref, rel=1e-12 if precision == LT.FP64 else 1e-6)
+    del red
+
+
+SAMPLED = [
+    ("droplet", lambda: WL.droplet(), 40, [(0, 96, 8000, 8100), (960, 1100, 7900, 7990), (1200, 1300, 0, 64),
+                                           (1950, 2048, 16300, 16384)]),
+    ("oblique", lambda: WL.poiseuille_oblique(), 60, [(0, 256, 0, 256)]),
+    ("annulus", lambda: WL.annular_shear(), 30, [(400, 520, 400, 520), (580, 660, 500, 560), (0, 64, 0, 64)]),
+    ("droplet_adjoint", lambda: WL.droplet_adjoint(), 40, [(200, 320, 960, 1090), (0, 60, 0, 60)]),
+    ("aligned", lambda: WL.poiseuille_aligned(), 2000, [(0, 4, 0, 100)]),
+]
+
+
+@pytest.mark.parametrize("precision", [LT.FP32_DEV, LT.FP64])
+@pytest.mark.parametrize("name,make,steps,windows", SAMPLED, ids=[s[0] for s in SAMPLED])
+def test_sampled_windows_at_full_size(name, make, steps, windows, precision):
+    w = make()
+    lat, g = run_gpu(w, steps, precision)
+    scale_u = max(np.max(np.abs(g["ux"])), np.max(np.abs(g["uy"])), 1e-12)
+    for (x0, x1, y0, y1) in windows:
+        print(f"[fullsize] oracle window {name} x[{x0},{x1}) y[{y0},{y1})", flush=True)
+        if name == "aligned":
+            o = O.Oracle(oracle_params(w)).init(w.rho0())
+            o.step(steps)
+            om = o.macros()
+            o = {k: om[k] for k in ("rho", "ux", "uy", "fintx", "finty", "psi")}
+        else:
+            o = crop_oracle(w, steps, x0, x1, y0, y1)
+        check(w, g, o, x0, x1, y0, y1, precision, scale_u)
