@@ -17,9 +17,9 @@
  *  - The stored state is the post-collision field.  A step streams then
  *    collides.  "Macroscopic fields of the current state" are the pre-collision
  *    fields the next step would use.
- *  - Precision LBM_FP64 stores f in double.  LBM_FP32_DEV stores
- *    f_i - w_i * rho_ref in float; the equation of state, the density and all
- *    reductions are evaluated in double, the rest of the step in float.
+ *  - Precision LBM_FP64 stores f in double.  LBM_FP32_DEV stores the
+ *    deviations f_i - w_i * rho_ref in float.  Both compute the step in double
+ *    (each population is rounded once when stored) and reduce in double.
  *  - Ownership: the caller allocates and frees every device buffer (the
  *    population arrays, the workspace, the mask, the wall velocities and all
  *    outputs).  The library never allocates or frees device memory; it keeps
@@ -169,6 +169,11 @@ int lbm_init_equilibrium(lbm_lattice* h, const double* rho0_dev, const double* u
  * stream is synchronised; a record with faults > 0 then makes the call return
  * LBM_ERR_EOS_DOMAIN or LBM_ERR_NONFINITE after the copy. */
 int lbm_step(lbm_lattice* h, int64_t n, int32_t reduce_every, lbm_reduction* out_host, int64_t n_out);
+
+/* Launch tuning of the fused kernels: rows each wavefront marches through
+ * (16 <= rows <= 4096; 0 restores the default chosen from the lattice size).
+ * Results do not depend on it. */
+int lbm_set_rows_per_wave(lbm_lattice* h, int32_t rows);
 
 /* Steps taken since lbm_init_equilibrium / lbm_set_state. */
 int lbm_step_count(const lbm_lattice* h, int64_t* steps);

@@ -162,6 +162,13 @@ bool all_finite(std::initializer_list<double> v) {
 
 void* state_ptr(lbm_lattice* h, int which) { return which == 0 ? h->buf.f_a : h->buf.f_b; }
 
+// The specialised strip kernel handles lattices without a mask or moving walls
+// whose population arrays fit 32-bit byte offsets.
+bool fast_path(const lbm_lattice* h) {
+  double bytes = 9.0 * (double)h->cfg.nx * (double)h->cfg.ny * (double)elem_size(&h->cfg);
+  return h->cfg.kernel == LBM_KERNEL_FUSED && !h->buf.mask && !h->buf.wall_u && bytes < 4294967040.0;
+}
+
 template <class T>
 hipError_t step_one(lbm_lattice* h, int reduce) {
   pplbm::StepLaunch L;
@@ -174,6 +181,7 @@ hipError_t step_one(lbm_lattice* h, int reduce) {
   L.kernel = h->cfg.kernel;
   L.seg_len = h->seg_len;
   L.reduce = reduce;
+  L.fast = fast_path(h) ? 1 : 0;
   return pplbm::launch_step<T>(h->prm, L, h->stream);
 }
 
@@ -429,6 +437,17 @@ int lbm_step(lbm_lattice* h, int64_t n, int32_t reduce_every, lbm_reduction* out
     }
     return status;
   }
+  return LBM_OK;
+}
+
+int lbm_set_rows_per_wave(lbm_lattice* h, int32_t rows) {
+  if (!h) return LBM_ERR_INVALID_ARG;
+  if (rows == 0) {
+    h->seg_len = default_seg_len(h->cfg.nx, h->cfg.ny);
+    return LBM_OK;
+  }
+  if (rows < kMinSegLen || rows > 4096) return fail(h, LBM_ERR_INVALID_ARG, "rows per wave must be in [16, 4096]");
+  h->seg_len = rows;
   return LBM_OK;
 }
 

@@ -18,6 +18,7 @@ struct StepLaunch {
   int kernel;         // 0 fused, 1 two-pass
   int seg_len;        // fused: rows per wavefront
   int reduce;         // 1: write reduction partials this step
+  int fast;           // fused: use the specialised strip kernel (no mask, no moving walls, 32-bit offsets)
 };
 
 int two_pass_blocks(int nx, int ny);

@@ -309,6 +309,280 @@ __global__ __launch_bounds__(256) void fused_kernel(StepParams p, const S* __res
   }
 }
 
+// ------------------------------------------------------------------ fast strip kernel
+//
+// The strip kernel specialised for lattices whose only walls are the planes
+// across non-periodic axes (no mask, no moving walls) and whose population
+// arrays fit 32-bit byte offsets.  Same arithmetic as fused_kernel; what
+// differs is the data movement:
+//  * loads and stores are buffer instructions whose offset is the plane and
+//    row (uniform) plus a lane-constant column; halfway bounce-back is a
+//    per-direction select of that offset, not a branch, and columns or rows
+//    that are not nodes read out of range (the buffer returns 0, stores are
+//    dropped), so the march has no divergent branches;
+//  * rows are software-pipelined: the loads of row y+2 are in flight while
+//    row y+1 gets its psi and row y collides;
+//  * psi of the neighbouring columns comes through DPP wavefront shifts;
+//  * blocks are numbered so that each XCD walks a contiguous range of row
+//    segments with the neighbouring strips of a segment side by side, so the
+//    columns two strips share stay in that XCD's L2.
+
+template <class S>
+struct BufIO;
+template <>
+struct BufIO<float> {
+  static __device__ inline float load(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0));
+  }
+  static __device__ inline void store(float v, __amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)byte_off, 0, 0);
+  }
+};
+template <>
+struct BufIO<double> {
+  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+  static __device__ inline double load(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0));
+  }
+  static __device__ inline void store(double v, __amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)byte_off, 0, 0);
+  }
+};
+
+// Lane l receives lane l-1's value (lane 0 keeps its own): DPP wave_shr:1.
+__device__ inline double wave_shr1(double v) {
+  unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  int lo = (int)(unsigned)b, hi = (int)(unsigned)(b >> 32);
+  lo = __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+// Lane l receives lane l+1's value (lane 63 keeps its own): DPP wave_shl:1.
+__device__ inline double wave_shl1(double v) {
+  unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  int lo = (int)(unsigned)b, hi = (int)(unsigned)(b >> 32);
+  lo = __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Row geometry, uniform across the wavefront.
+struct RowGeo {
+  bool real;         // the row is a lattice row (in the box, or wrapped periodically)
+  unsigned own, bot, top;  // element offsets of rows y, y-1, y+1 (times nx)
+  bool wall_b, wall_t;     // y-1 / y+1 lie beyond a non-periodic edge
+};
+
+__device__ inline RowGeo row_geo(const StepParams& p, int y) {
+  RowGeo g;
+  int yw = y;
+  g.real = true;
+  if (y < 0 || y >= p.ny) {
+    if (p.periodic_y)
+      yw = y < 0 ? y + p.ny : y - p.ny;
+    else
+      g.real = false, yw = 0;
+  }
+  int yb = yw - 1, yt = yw + 1;
+  g.wall_b = g.wall_t = false;
+  if (yb < 0) {
+    if (p.periodic_y) yb += p.ny;
+    else g.wall_b = true, yb = 0;
+  }
+  if (yt >= p.ny) {
+    if (p.periodic_y) yt -= p.ny;
+    else g.wall_t = true, yt = 0;
+  }
+  g.own = (unsigned)yw * (unsigned)p.nx;
+  g.bot = (unsigned)yb * (unsigned)p.nx;
+  g.top = (unsigned)yt * (unsigned)p.nx;
+  return g;
+}
+
+// Lane geometry, constant along the march.
+struct ColGeo {
+  bool real;
+  unsigned own, left, right;  // wrapped columns x, x-1, x+1
+  bool wall_l, wall_r;
+};
+
+// Byte offsets of the 9 pulled populations of node (row g, column c);
+// `oob` (>= the buffer size) for a node that does not exist.
+template <class S>
+__device__ inline void pull_offsets(const RowGeo& g, const ColGeo& c, unsigned N, unsigned oob, unsigned off[9]) {
+  const unsigned own = g.own + c.own;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int exi = ex(i), eyi = ey(i);
+    const unsigned row = eyi == 1 ? g.bot : (eyi == -1 ? g.top : g.own);
+    const unsigned col = exi == 1 ? c.left : (exi == -1 ? c.right : c.own);
+    const bool wall = (eyi == 1 && g.wall_b) || (eyi == -1 && g.wall_t) || (exi == 1 && c.wall_l) ||
+                      (exi == -1 && c.wall_r);
+    const unsigned e = wall ? (unsigned)opp(i) * N + own : (unsigned)i * N + row + col;
+    off[i] = (g.real && c.real) ? e * (unsigned)sizeof(S) : oob;
+  }
+}
+
+template <class S>
+__device__ inline void load_row(__amdgpu_buffer_rsrc_t in, const unsigned off[9], S v[9]) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) v[i] = BufIO<S>::load(in, off[i]);
+}
+
+// Density deviation, momentum and psi of a pulled row (psi_solid where the
+// node does not exist).
+template <class S>
+__device__ inline void row_state(const StepParams& p, const S raw[9], bool exists, double& drho, double& jx,
+                                 double& jy, double& psi, bool& bad) {
+  double d[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) d[i] = (double)raw[i];
+  node_sums(d, drho, jx, jy);
+  double ps = psi_of(p, p.rho_ref + drho, bad);
+  psi = exists ? ps : p.psi_solid;
+  bad = exists && bad;
+}
+
+template <class S, bool REDUCE>
+__global__ __launch_bounds__(256) void fast_kernel(StepParams p, const S* __restrict__ f, S* __restrict__ fo,
+                                                   int n_strips, int seg_len, int n_segs, int groups, int per_xcd,
+                                                   double* __restrict__ partials) {
+  const int b = blockIdx.x;
+  const int L = (b & 7) * per_xcd + (b >> 3);
+  const int seg = L / groups;
+  const int group = L - seg * groups;
+  const int wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int strip = group * 4 + wv;
+  if (seg >= n_segs || strip >= n_strips) return;  // uniform per wavefront
+
+  const int nx = p.nx;
+  const unsigned N = (unsigned)nx * (unsigned)p.ny;
+  const unsigned bytes = 9u * N * (unsigned)sizeof(S);
+  const __amdgpu_buffer_rsrc_t in = __builtin_amdgcn_make_buffer_rsrc((void*)f, (short)0, (int)bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t out = __builtin_amdgcn_make_buffer_rsrc((void*)fo, (short)0, (int)bytes, 0x00020000);
+
+  // lane geometry
+  const int x = strip * STRIP - 1 + lane;
+  ColGeo c;
+  int xw = x;
+  c.real = true;
+  if (x < 0 || x >= nx) {
+    if (p.periodic_x && (x == -1 || x == nx))
+      xw = x < 0 ? nx - 1 : 0;
+    else
+      c.real = false, xw = 0;
+  }
+  int xl = xw - 1, xr = xw + 1;
+  c.wall_l = c.wall_r = false;
+  if (xl < 0) {
+    if (p.periodic_x) xl += nx;
+    else c.wall_l = true, xl = 0;
+  }
+  if (xr >= nx) {
+    if (p.periodic_x) xr -= nx;
+    else c.wall_r = true, xr = 0;
+  }
+  c.own = (unsigned)xw;
+  c.left = (unsigned)xl;
+  c.right = (unsigned)xr;
+  const bool owner = lane >= 1 && lane <= STRIP && x < nx;
+
+  const int y0 = seg * seg_len;
+  const int y1 = min(y0 + seg_len, p.ny);
+
+  double acc[RED_COUNT];
+#pragma unroll
+  for (int q = 0; q < RED_COUNT; ++q) acc[q] = 0.0;
+
+  S r0[9], r1[9], r2[9];
+  unsigned off[9];
+  double dr0, jx0, jy0, ps0, dr1, jx1, jy1, ps1, psm;
+  bool bad0, bad1, badm;
+
+  // prologue: halo row y0-1 (psi only), rows y0 and y0+1 in flight
+  RowGeo gm = row_geo(p, y0 - 1);
+  pull_offsets<S>(gm, c, N, bytes, off);
+  load_row<S>(in, off, r2);
+  RowGeo g0 = row_geo(p, y0);
+  pull_offsets<S>(g0, c, N, bytes, off);
+  load_row<S>(in, off, r0);
+  RowGeo g1 = row_geo(p, y0 + 1);
+  pull_offsets<S>(g1, c, N, bytes, off);
+  load_row<S>(in, off, r1);
+  {
+    double a, bb, cc;
+    row_state<S>(p, r2, gm.real && c.real, a, bb, cc, psm, badm);
+  }
+  row_state<S>(p, r0, g0.real && c.real, dr0, jx0, jy0, ps0, bad0);
+
+  for (int y = y0; y < y1; ++y) {
+    // issue the loads of row y+2 (needed from the next iteration on)
+    RowGeo g2 = row_geo(p, y + 2);
+    if (y + 2 <= y1) {
+      pull_offsets<S>(g2, c, N, bytes, off);
+      load_row<S>(in, off, r2);
+    }
+    // row y+1: density, momentum, psi
+    row_state<S>(p, r1, g1.real && c.real, dr1, jx1, jy1, ps1, bad1);
+    // neighbours' psi (every lane executes the shifts)
+    const double pW = wave_shr1(ps0), pE = wave_shl1(ps0);
+    const double pSW = wave_shr1(psm), pSE = wave_shl1(psm);
+    const double pNW = wave_shr1(ps1), pNE = wave_shl1(ps1);
+    // row y: collide and store
+    double d[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) d[i] = (double)r0[i];
+    double Sx, Sy;
+    stencil_sums(pE, ps1, pW, psm, pNE, pNW, pSW, pSE, Sx, Sy);
+    NodeMacro mac = collide_node(p, d, dr0, jx0, jy0, ps0, Sx, Sy);
+    const bool store = owner && g0.real;
+    const unsigned k = g0.own + c.own;
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+      BufIO<S>::store((S)d[i], out, store ? ((unsigned)i * N + k) * (unsigned)sizeof(S) : bytes);
+    if (REDUCE && store) {
+      // bounce-back links of this node: the wall received -(f_i + fbar_opp) e_i = -2 f_i e_i
+      double wx = 0.0, wy = 0.0;
+#pragma unroll
+      for (int i = 1; i < 9; ++i) {
+        const int exi = ex(i), eyi = ey(i);
+        const bool wall = (eyi == 1 && g0.wall_b) || (eyi == -1 && g0.wall_t) || (exi == 1 && c.wall_l) ||
+                          (exi == -1 && c.wall_r);
+        if (wall) {
+          double both = 2.0 * ((double)r0[i] + wgt(i) * p.rho_ref);
+          wx -= exi * both;
+          wy -= eyi * both;
+        }
+      }
+      acc[RED_WALLX] += wx;
+      acc[RED_WALLY] += wy;
+      accumulate_node(p, acc, p.rho_ref + dr0, jx0, jy0, mac, bad0);
+    }
+    // rotate the pipeline
+    psm = ps0;
+    ps0 = ps1;
+    dr0 = dr1;
+    jx0 = jx1;
+    jy0 = jy1;
+    bad0 = bad1;
+    g0 = g1;
+    g1 = g2;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      r0[i] = r1[i];
+      r1[i] = r2[i];
+    }
+  }
+  if (REDUCE) {
+#pragma unroll
+    for (int q = 0; q < RED_COUNT; ++q) {
+      double v = wave_sum(acc[q]);
+      if (lane == 0) partials[(size_t)(seg * n_strips + strip) * RED_COUNT + q] = v;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ finalize
 __global__ void finalize_kernel(const double* __restrict__ partials, int n_parts, double* __restrict__ out) {
   __shared__ double lds[RED_COUNT][256];
@@ -367,6 +641,18 @@ hipError_t launch_step(const StepParams& p, const StepLaunch& L, hipStream_t st)
     else
       hipLaunchKernelGGL((collide_kernel<S, false>), grd, blk, 0, st, p, f, fo, L.mask, L.wall_u,
                          (const double*)L.psi, L.partials);
+  } else if (L.fast) {
+    int n_strips, n_segs;
+    fused_shape(p.nx, p.ny, L.seg_len, &n_strips, &n_segs);
+    int groups = (n_strips + 3) / 4;
+    int total = groups * n_segs;
+    int per_xcd = (total + 7) / 8;
+    if (L.reduce)
+      hipLaunchKernelGGL((fast_kernel<S, true>), dim3(8 * per_xcd), dim3(256), 0, st, p, f, fo, n_strips, L.seg_len,
+                         n_segs, groups, per_xcd, L.partials);
+    else
+      hipLaunchKernelGGL((fast_kernel<S, false>), dim3(8 * per_xcd), dim3(256), 0, st, p, f, fo, n_strips, L.seg_len,
+                         n_segs, groups, per_xcd, L.partials);
   } else {
     int n_strips, n_segs;
     fused_shape(p.nx, p.ny, L.seg_len, &n_strips, &n_segs);

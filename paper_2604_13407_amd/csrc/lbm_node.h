@@ -31,16 +31,50 @@ __host__ __device__ constexpr double wgt(int i) { return i == 0 ? 4.0 / 9.0 : (i
 static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "opposites");
 static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "opposites");
 
+// 1/a to within about one ulp: the hardware reciprocal estimate refined by two
+// Newton-Raphson steps (e <- 1 - a r, r <- r + r e).
+__host__ __device__ inline double recip(double a) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(a);
+  double e = __builtin_fma(-a, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-a, r, 1.0);
+  return __builtin_fma(r, e, r);
+#else
+  return 1.0 / a;
+#endif
+}
+
+// sqrt(q), 0 for q <= 0: the reciprocal-square-root estimate y, then one
+// coupled Newton step on g = q y ~ sqrt(q) and h = y/2 ~ 1/(2 sqrt(q))
+// (Goldschmidt's iteration) and a final residual correction g + (q - g^2) h.
+__host__ __device__ inline double root(double q) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double qq = q > 0.0 ? q : 1.0;
+  double y = __builtin_amdgcn_rsq(qq);
+  double g = qq * y;
+  double h = 0.5 * y;
+  double r = __builtin_fma(-g, h, 0.5);
+  g = __builtin_fma(g, r, g);
+  h = __builtin_fma(h, r, h);
+  r = __builtin_fma(-g, g, qq);
+  g = __builtin_fma(r, h, g);
+  return q > 0.0 ? g : 0.0;
+#else
+  return q > 0.0 ? sqrt(q) : 0.0;
+#endif
+}
+
 // psi^2 = 2 (rho c_s^2 - p_EOS), evaluated in double (the difference cancels
 // strongly in the vapour).  Van der Waals (Eq. 43) or Carnahan-Starling.
 __device__ __host__ inline double psi_squared(const StepParams& p, double r) {
   double pe;
   if (p.eos_kind == 0) {
-    pe = p.k_eos * (r * p.RT / (1.0 - p.b * r) - p.a * r * r);
+    pe = p.k_eos * (r * p.RT * recip(1.0 - p.b * r) - p.a * r * r);
   } else {
     double eta = 0.25 * p.b * r;
     double om = 1.0 - eta;
-    pe = p.k_eos * (r * p.RT * (1.0 + eta * (1.0 + eta * (1.0 - eta))) / (om * om * om) - p.a * r * r);
+    pe = p.k_eos * (r * p.RT * (1.0 + eta * (1.0 + eta * (1.0 - eta))) * recip(om * om * om) - p.a * r * r);
   }
   return 2.0 * (r * (1.0 / 3.0) - pe);
 }
@@ -49,7 +83,7 @@ __device__ __host__ inline double psi_squared(const StepParams& p, double r) {
 __host__ __device__ inline double psi_of(const StepParams& p, double r, bool& bad) {
   double q = psi_squared(p, r);
   bad = !(q >= 0.0) || !(r > 0.0);
-  return sqrt(q > 0.0 ? q : 0.0);
+  return root(q);
 }
 
 // Whether lattice position (x, y) (possibly one step outside the box) is
@@ -174,8 +208,9 @@ __host__ __device__ inline NodeMacro collide_node(const StepParams& p, double d[
     Fx = Fix + p.fx;
     Fy = Fiy + p.fy;
   }
-  const double ux = (jx + 0.5 * Fx) / r;
-  const double uy = (jy + 0.5 * Fy) / r;
+  const double inv_r = recip(r);
+  const double ux = (jx + 0.5 * Fx) * inv_r;
+  const double uy = (jy + 0.5 * Fy) * inv_r;
 
   // moments of the pulled deviations
   const double d0 = d[0];

@@ -34,6 +34,7 @@ RED_FIELDS = ("mass", "mom_x", "mom_y", "wall_x", "wall_y", "uc_num", "uc_den", 
 EXPORTS = ("lbm_abi_version", "lbm_state_bytes", "lbm_workspace_bytes", "lbm_create", "lbm_destroy",
            "lbm_last_error", "lbm_set_eos", "lbm_set_G", "lbm_set_relaxation", "lbm_set_scheme",
            "lbm_set_body_force", "lbm_set_phase_densities", "lbm_set_walls", "lbm_init_equilibrium", "lbm_step",
+           "lbm_set_rows_per_wave",
            "lbm_step_count", "lbm_read_fields", "lbm_reduce", "lbm_state_ptr", "lbm_get_state", "lbm_set_state")
 
 
@@ -91,6 +92,7 @@ def lib():
         L.lbm_init_equilibrium.argtypes = [vp, vp, vp, vp]
         L.lbm_step.argtypes = [vp, C.c_int64, C.c_int32, C.POINTER(Reduction), C.c_int64]
         L.lbm_step_count.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.lbm_set_rows_per_wave.argtypes = [vp, C.c_int32]
         L.lbm_read_fields.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.lbm_reduce.argtypes = [vp, C.POINTER(Reduction)]
         L.lbm_state_ptr.argtypes = [vp, C.POINTER(vp)]
@@ -188,6 +190,10 @@ class Lattice:
 
     def set_walls(self, rho_s: float):
         self._check(lib().lbm_set_walls(self.h, rho_s), self.h)
+
+    def set_rows_per_wave(self, rows: int):
+        """Launch tuning of the fused kernels (0 = default); results do not depend on it."""
+        self._check(lib().lbm_set_rows_per_wave(self.h, rows), self.h)
 
     # ------------------------------------------------------------ state
     def init_equilibrium(self, rho0, ux0=None, uy0=None):

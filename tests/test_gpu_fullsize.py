@@ -15,6 +15,7 @@ from oracle import oracle as O
 from paper_2604_13407_amd import lattice as LT
 from paper_2604_13407_amd import workloads as WL
 from tests.helpers import oracle_params
+from tests.test_gpu_parity import U_FLOOR
 
 pytestmark = pytest.mark.gpu
 
@@ -63,9 +64,10 @@ def check(w, g, o, x0, x1, y0, y1, precision, scale_u):
     mask = w.mask()
     fl = np.ones((y1 - y0, x1 - x0), bool) if mask is None else (mask[y0:y1, x0:x1] == 0)
     gw = {k: g[k][y0:y1, x0:x1] for k in o}
+    assert fl.any(), "window without fluid nodes"
     if precision == LT.FP64:
         for k in ("rho", "ux", "uy", "psi"):
-            sc = scale_u if k in ("ux", "uy") else np.max(np.abs(o[k][fl]))
+            sc = max(scale_u, U_FLOOR) if k in ("ux", "uy") else np.max(np.abs(o[k][fl]))
             err = np.max(np.abs(gw[k][fl] - o[k][fl])) / sc
             assert err <= 1e-12, (w.name, k, err)
     else:
@@ -89,8 +91,11 @@ def test_droplet_full_lattice_few_steps(precision):
     check(w, g, {k: om[k] for k in ("rho", "ux", "uy", "fintx", "finty", "psi")}, 0, w.nx, 0, w.ny, precision,
           scale_u)
     rec = lat.reduce()
-    mass_ref = om["red"]["mass"]
+    # reference mass by pairwise summation of the oracle's node densities (the
+    # oracle's own serial sum over 3.4e7 nodes carries ~1e-9 relative round-off)
+    mass_ref = float(np.sum(om["rho"]))
     assert rec["mass"] == pytest.approx(mass_ref, rel=1e-12 if precision == LT.FP64 else 1e-6)
+    assert om["red"]["mass"] == pytest.approx(mass_ref, rel=1e-8)
     del red
 
 
@@ -98,7 +103,7 @@ SAMPLED = [
     ("droplet", lambda: WL.droplet(), 40, [(0, 96, 8000, 8100), (960, 1100, 7900, 7990), (1200, 1300, 0, 64),
                                            (1950, 2048, 16300, 16384)]),
     ("oblique", lambda: WL.poiseuille_oblique(), 60, [(0, 256, 0, 256)]),
-    ("annulus", lambda: WL.annular_shear(), 30, [(400, 520, 400, 520), (580, 660, 500, 560), (0, 64, 0, 64)]),
+    ("annulus", lambda: WL.annular_shear(), 30, [(400, 520, 400, 520), (580, 660, 500, 560), (20, 100, 470, 550)]),
     ("droplet_adjoint", lambda: WL.droplet_adjoint(), 40, [(200, 320, 960, 1090), (0, 60, 0, 60)]),
     ("aligned", lambda: WL.poiseuille_aligned(), 2000, [(0, 4, 0, 100)]),
 ]
