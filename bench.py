@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Throughput of the pseudopotential MRT lattice Boltzmann step on one MI355X.
+
+Workload: the falling-droplet channel, 2048 x 16384 nodes (bounce-back walls
+at x = -1/2 and 2047.5, periodic in y), Carnahan-Starling EOS at 0.7 T_c, a
+liquid droplet of radius 256, buoyant gravity (rho - rho_g)(0, -1e-7),
+improved third-order scheme, eps = 1.895, observables reduced every 100
+steps.  Populations stored as FP32 deviations (the headline) and in FP64.
+
+Prints one JSON line: MLUPS (million lattice-node updates per second) of the
+FP32-storage path, the HBM roofline of its step kernel (algorithmic bytes per
+node: 9 reads + 9 writes of the stored type), the FP64 path, the original
+scheme, and the FP64 CPU oracle timed on a bounded sample on the host cores.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+ROOT = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "fast_kernel_fp32_droplet_2048x16384.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE record, or None when the kernel sources changed
+    since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_RECORD))
+        h = hashlib.sha256()
+        for src in rec["kernel_sources"]:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+        if h.hexdigest() != rec["kernel_sources_sha256"]:
+            return None
+        return rec["traffic_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="time only the FP32 headline path")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of known size (for HBM counter scaling)")
+    return ap.parse_args()
+
+
+def time_steps(lat, steps, reduce_every):
+    import torch
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(lat.stream)
+    lat.step(steps, reduce_every=reduce_every)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1), wall
+
+
+def gpu_run(w, precision, steps, warmup, reduce_every):
+    import torch
+    from paper_2604_13407_amd import lattice as LT
+    lat = LT.Lattice.from_workload(w, precision=precision, kernel=LT.KERNEL_FUSED)
+    if warmup:
+        lat.step(warmup, reduce_every=reduce_every)
+    ms, wall = time_steps(lat, steps, reduce_every)
+    rec = lat.reduce()
+    out = {"ms_per_step": ms / steps, "wall_s": wall, "mass": rec["mass"], "faults": rec["faults"]}
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(w, target_s=12.0):
+    """The FP64 oracle on a band of the same lattice (full width, 512 rows
+    through the droplet), as many steps as fit in about target_s seconds."""
+    import numpy as np
+    from oracle import oracle as O
+    band = 512
+    y0 = w.ny // 2 - band // 2
+    rho0 = np.ascontiguousarray(w.rho0()[y0:y0 + band])
+    p = O.Params(nx=w.nx, ny=band, periodic_x=w.periodic_x, periodic_y=w.periodic_y, eos_kind=w.eos_kind, a=w.a,
+                 b=w.b, R=w.R, T=w.T, k_eos=w.k_eos, G=w.G, s=tuple(w.s), scheme=w.scheme, eps=w.eps, k1=w.k1,
+                 k2=w.k2, force_mode=w.force_mode, fx=w.fx, fy=w.fy, rho_g=w.rho_g, rho_l=w.rho_l, rho_s=w.rho_s)
+    o = O.Oracle(p).init(rho0)
+    threads = O.lib().oracle_threads(0)
+    o.step(1)  # warm-up
+    t0 = time.perf_counter()
+    o.step(2)
+    per_step = (time.perf_counter() - t0) / 2
+    n = max(2, int(target_s / per_step))
+    t0 = time.perf_counter()
+    o.step(n)
+    dt = time.perf_counter() - t0
+    nodes = w.nx * band
+    return {"value": nodes * n / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle, {w.nx}x{band} band of the droplet lattice (rows {y0}..{y0 + band - 1}, "
+                      f"walls in x, periodic in y), {n} steps, {dt:.1f} s, {threads} threads"}
+
+
+def copy_calibration():
+    """A plain device-to-device copy of 1 GiB (read 1 GiB, write 1 GiB), for
+    scaling the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"bytes_read": 1 << 30, "bytes_written": 1 << 30, "launches": 3}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is described, not built)", file=sys.stderr)
+        sys.exit(2)
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import torch
+    from paper_2604_13407_amd import lattice as LT
+    from paper_2604_13407_amd import workloads as WL
+
+    w = WL.droplet()
+    reduce_every = w.reduce_every
+    steps, warmup = args.steps, args.warmup
+
+    head = gpu_run(w, LT.FP32_DEV, steps, warmup, reduce_every)
+    ms = head["ms_per_step"]
+    mlups = w.nodes / (ms * 1e-3) / 1e6
+    bytes_per_node = 9 * 4 * 2  # 9 loads + 9 stores of float per node update
+    achieved = w.nodes * bytes_per_node / (ms * 1e-3) / 1e9
+
+    result = {
+        "metric": "MLUPS + % HBM roofline, FP32 vs FP64 (improved scheme); adjoint/forward cost",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "storage": "f32 deviations from w_i*rho_ref",
+        "data": "synthetic",
+        "config": {"workload": "droplet channel 2048x16384, CS EOS T=0.7Tc, R=256 droplet, buoyant g=1e-7, "
+                               "improved scheme eps=1.895, reductions every 100 steps",
+                   "nx": w.nx, "ny": w.ny, "scheme": "improved", "reduce_every": reduce_every,
+                   "kernel": "fused strip (fast path)"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                     "bytes_per_node": bytes_per_node,
+                     "note": "achieved = 72 B/node x nodes / average step-kernel duration (HIP events over "
+                             "the timed region, on the lattice's stream); traffic = HBM bytes per launch from "
+                             "rocprofv3 FETCH_SIZE/WRITE_SIZE scaled by a plain copy (profiles/)"},
+    }
+    if head["faults"]:
+        result["faults"] = head["faults"]
+
+    if not args.no_extra:
+        fp64 = gpu_run(w, LT.FP64, steps, warmup, reduce_every)
+        m64 = w.nodes / (fp64["ms_per_step"] * 1e-3) / 1e6
+        a64 = w.nodes * 144 / (fp64["ms_per_step"] * 1e-3) / 1e9
+        result["fp64"] = {"value": round(m64, 1), "unit": "MLUPS", "ms_per_step": round(fp64["ms_per_step"], 5),
+                          "achieved_GBs": round(a64, 1), "frac": round(a64 / HBM_PEAK_GBS, 4),
+                          "bytes_per_node": 144}
+        orig = gpu_run(WL.droplet(scheme=WL.SCHEME_ORIGINAL), LT.FP32_DEV, steps, warmup, reduce_every)
+        result["original_scheme"] = {"value": round(w.nodes / (orig["ms_per_step"] * 1e-3) / 1e6, 1),
+                                     "unit": "MLUPS", "ms_per_step": round(orig["ms_per_step"], 5)}
+
+    if args.copy_calibration:
+        result["copy_calibration"] = copy_calibration()
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(w)
+        result["gpu_over_cpu"] = round(mlups / result["cpu_baseline"]["value"], 1)
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -429,18 +429,191 @@ __device__ inline void load_row(__amdgpu_buffer_rsrc_t in, const unsigned off[9]
   for (int i = 0; i < 9; ++i) v[i] = BufIO<S>::load(in, off[i]);
 }
 
+// Per-row quantities carried between pipeline stages.
+struct RowScal {
+  double drho, jx, jy, psi;
+  bool bad;
+  RowGeo g;
+};
+
 // Density deviation, momentum and psi of a pulled row (psi_solid where the
 // node does not exist).
 template <class S>
-__device__ inline void row_state(const StepParams& p, const S raw[9], bool exists, double& drho, double& jx,
-                                 double& jy, double& psi, bool& bad) {
+__device__ inline void row_state(const StepParams& p, const S raw[9], bool exists, RowScal& t) {
   double d[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) d[i] = (double)raw[i];
-  node_sums(d, drho, jx, jy);
-  double ps = psi_of(p, p.rho_ref + drho, bad);
-  psi = exists ? ps : p.psi_solid;
-  bad = exists && bad;
+  node_sums(d, t.drho, t.jx, t.jy);
+  bool bad;
+  double ps = psi_of(p, p.rho_ref + t.drho, bad);
+  t.psi = exists ? ps : p.psi_solid;
+  t.bad = exists && bad;
+}
+
+// March state of one wavefront.
+struct March {
+  __amdgpu_buffer_rsrc_t in, out;
+  unsigned N, bytes;
+  ColGeo c;
+  bool owner;
+  int y1;
+  // lane-constant byte offset of the pulled column for each direction
+  unsigned colB[9];
+};
+
+// Byte offsets of row y's pulled populations for an interior strip of a
+// y-periodic lattice: plane + source row (uniform) + source column (lane).
+template <class S>
+__device__ inline void pull_offsets_interior(const March& m, const RowGeo& g, unsigned off[9]) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int eyi = ey(i);
+    const unsigned row = eyi == 1 ? g.bot : (eyi == -1 ? g.top : g.own);
+    off[i] = ((unsigned)i * m.N + row) * (unsigned)sizeof(S) + m.colB[i];
+  }
+}
+
+template <class S, bool INTERIOR>
+__device__ inline void issue_row(const StepParams& p, const March& m, int y, S raw[9], RowGeo& g) {
+  g = row_geo(p, y);
+  unsigned off[9];
+  if (INTERIOR)
+    pull_offsets_interior<S>(m, g, off);
+  else
+    pull_offsets<S>(g, m.c, m.N, m.bytes, off);
+  load_row<S>(m.in, off, raw);
+}
+
+// One row of the march: issue the loads of row y+2 into `nxt`, finish row y+1
+// (`cur1` into `t1`), then collide and store row y (`cur0`, `t0`) with psi of
+// row y-1 from `tm`.
+template <class S, bool REDUCE, bool INTERIOR>
+__device__ inline void march_row(const StepParams& p, const March& m, int y, const S cur0[9], const S cur1[9],
+                                 S nxt[9], const RowScal& tm, const RowScal& t0, RowScal& t1, RowScal& t2,
+                                 double* acc) {
+  if (y + 2 <= m.y1) issue_row<S, INTERIOR>(p, m, y + 2, nxt, t2.g);
+  row_state<S>(p, cur1, t1.g.real && m.c.real, t1);
+  const double pW = wave_shr1(t0.psi), pE = wave_shl1(t0.psi);
+  const double pSW = wave_shr1(tm.psi), pSE = wave_shl1(tm.psi);
+  const double pNW = wave_shr1(t1.psi), pNE = wave_shl1(t1.psi);
+  double d[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) d[i] = (double)cur0[i];
+  double Sx, Sy;
+  stencil_sums(pE, t1.psi, pW, tm.psi, pNE, pNW, pSW, pSE, Sx, Sy);
+  NodeMacro mac = collide_node(p, d, t0.drho, t0.jx, t0.jy, t0.psi, Sx, Sy);
+  const bool store = m.owner && t0.g.real;
+  const unsigned k = t0.g.own + m.c.own;
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+    BufIO<S>::store((S)d[i], m.out, store ? ((unsigned)i * m.N + k) * (unsigned)sizeof(S) : m.bytes);
+  if (REDUCE && store) {
+    if (!INTERIOR) {
+      // bounce-back links: the wall received -(f_i + fbar_opp) e_i = -2 f_i e_i
+      double wx = 0.0, wy = 0.0;
+#pragma unroll
+      for (int i = 1; i < 9; ++i) {
+        const int exi = ex(i), eyi = ey(i);
+        const bool wall = (eyi == 1 && t0.g.wall_b) || (eyi == -1 && t0.g.wall_t) || (exi == 1 && m.c.wall_l) ||
+                          (exi == -1 && m.c.wall_r);
+        if (wall) {
+          double both = 2.0 * ((double)cur0[i] + wgt(i) * p.rho_ref);
+          wx -= exi * both;
+          wy -= eyi * both;
+        }
+      }
+      acc[RED_WALLX] += wx;
+      acc[RED_WALLY] += wy;
+    }
+    accumulate_node(p, acc, p.rho_ref + t0.drho, t0.jx, t0.jy, mac, t0.bad);
+  }
+}
+
+// Depth-2 pipeline: rows y+1 and y+2 are in flight when row y collides; the
+// loads of row y+3 go into the slot of row y-1.
+template <class S, bool REDUCE, bool INTERIOR>
+__device__ inline void march_row4(const StepParams& p, const March& m, int y, const S cur0[9], const S cur1[9],
+                                  S nxt[9], const RowScal& tm, const RowScal& t0, RowScal& t1, RowScal& t3,
+                                  double* acc) {
+  if (y + 3 <= m.y1) issue_row<S, INTERIOR>(p, m, y + 3, nxt, t3.g);
+  row_state<S>(p, cur1, t1.g.real && m.c.real, t1);
+  const double pW = wave_shr1(t0.psi), pE = wave_shl1(t0.psi);
+  const double pSW = wave_shr1(tm.psi), pSE = wave_shl1(tm.psi);
+  const double pNW = wave_shr1(t1.psi), pNE = wave_shl1(t1.psi);
+  double d[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) d[i] = (double)cur0[i];
+  double Sx, Sy;
+  stencil_sums(pE, t1.psi, pW, tm.psi, pNE, pNW, pSW, pSE, Sx, Sy);
+  NodeMacro mac = collide_node(p, d, t0.drho, t0.jx, t0.jy, t0.psi, Sx, Sy);
+  const bool store = m.owner && t0.g.real;
+  const unsigned k = t0.g.own + m.c.own;
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+    BufIO<S>::store((S)d[i], m.out, store ? ((unsigned)i * m.N + k) * (unsigned)sizeof(S) : m.bytes);
+  if (REDUCE && store) {
+    if (!INTERIOR) {
+      double wx = 0.0, wy = 0.0;
+#pragma unroll
+      for (int i = 1; i < 9; ++i) {
+        const int exi = ex(i), eyi = ey(i);
+        const bool wall = (eyi == 1 && t0.g.wall_b) || (eyi == -1 && t0.g.wall_t) || (exi == 1 && m.c.wall_l) ||
+                          (exi == -1 && m.c.wall_r);
+        if (wall) {
+          double both = 2.0 * ((double)cur0[i] + wgt(i) * p.rho_ref);
+          wx -= exi * both;
+          wy -= eyi * both;
+        }
+      }
+      acc[RED_WALLX] += wx;
+      acc[RED_WALLY] += wy;
+    }
+    accumulate_node(p, acc, p.rho_ref + t0.drho, t0.jx, t0.jy, mac, t0.bad);
+  }
+}
+// The march over rows y0..y1-1.  Pulled rows live in a ring of slots unrolled
+// in the loop body, so no register is copied from one slot to the next:
+// float storage uses three slots (row y+2 in flight while row y collides),
+// double storage four (rows y+2 and y+3 in flight; each row is twice the
+// bytes, so the deeper pipeline is what keeps enough loads outstanding).
+template <class S, bool REDUCE, bool INTERIOR>
+__device__ inline void march(const StepParams& p, const March& m, int y0, double* acc) {
+  if (sizeof(S) == 4) {
+    S ra[9], rb[9], rc[9];
+    RowScal ta, tb, tc;
+    // row r lives in slot (r - y0 + 1) mod 3: y0-1 -> c, y0 -> a, y0+1 -> b
+    issue_row<S, INTERIOR>(p, m, y0 - 1, rc, tc.g);
+    issue_row<S, INTERIOR>(p, m, y0, ra, ta.g);
+    issue_row<S, INTERIOR>(p, m, y0 + 1, rb, tb.g);
+    row_state<S>(p, rc, tc.g.real && m.c.real, tc);
+    row_state<S>(p, ra, ta.g.real && m.c.real, ta);
+    for (int y = y0; y < m.y1; y += 3) {
+      march_row<S, REDUCE, INTERIOR>(p, m, y, ra, rb, rc, tc, ta, tb, tc, acc);
+      if (y + 1 >= m.y1) break;
+      march_row<S, REDUCE, INTERIOR>(p, m, y + 1, rb, rc, ra, ta, tb, tc, ta, acc);
+      if (y + 2 >= m.y1) break;
+      march_row<S, REDUCE, INTERIOR>(p, m, y + 2, rc, ra, rb, tb, tc, ta, tb, acc);
+    }
+  } else {
+    S r0[9], r1[9], r2[9], r3[9];
+    RowScal t0, t1, t2, t3;
+    // row r lives in slot (r - y0 + 1) mod 4: y0-1 -> 0, y0 -> 1, y0+1 -> 2, y0+2 -> 3
+    issue_row<S, INTERIOR>(p, m, y0 - 1, r0, t0.g);
+    issue_row<S, INTERIOR>(p, m, y0, r1, t1.g);
+    issue_row<S, INTERIOR>(p, m, y0 + 1, r2, t2.g);
+    if (y0 + 2 <= m.y1) issue_row<S, INTERIOR>(p, m, y0 + 2, r3, t3.g);
+    row_state<S>(p, r0, t0.g.real && m.c.real, t0);
+    row_state<S>(p, r1, t1.g.real && m.c.real, t1);
+    for (int y = y0; y < m.y1; y += 4) {
+      march_row4<S, REDUCE, INTERIOR>(p, m, y, r1, r2, r0, t0, t1, t2, t0, acc);
+      if (y + 1 >= m.y1) break;
+      march_row4<S, REDUCE, INTERIOR>(p, m, y + 1, r2, r3, r1, t1, t2, t3, t1, acc);
+      if (y + 2 >= m.y1) break;
+      march_row4<S, REDUCE, INTERIOR>(p, m, y + 2, r3, r0, r2, t2, t3, t0, t2, acc);
+      if (y + 3 >= m.y1) break;
+      march_row4<S, REDUCE, INTERIOR>(p, m, y + 3, r0, r1, r3, t3, t0, t1, t3, acc);
+    }
+  }
 }
 
 template <class S, bool REDUCE>
@@ -457,14 +630,15 @@ __global__ __launch_bounds__(256) void fast_kernel(StepParams p, const S* __rest
   if (seg >= n_segs || strip >= n_strips) return;  // uniform per wavefront
 
   const int nx = p.nx;
-  const unsigned N = (unsigned)nx * (unsigned)p.ny;
-  const unsigned bytes = 9u * N * (unsigned)sizeof(S);
-  const __amdgpu_buffer_rsrc_t in = __builtin_amdgcn_make_buffer_rsrc((void*)f, (short)0, (int)bytes, 0x00020000);
-  const __amdgpu_buffer_rsrc_t out = __builtin_amdgcn_make_buffer_rsrc((void*)fo, (short)0, (int)bytes, 0x00020000);
+  March m;
+  m.N = (unsigned)nx * (unsigned)p.ny;
+  m.bytes = 9u * m.N * (unsigned)sizeof(S);
+  m.in = __builtin_amdgcn_make_buffer_rsrc((void*)f, (short)0, (int)m.bytes, 0x00020000);
+  m.out = __builtin_amdgcn_make_buffer_rsrc((void*)fo, (short)0, (int)m.bytes, 0x00020000);
 
   // lane geometry
   const int x = strip * STRIP - 1 + lane;
-  ColGeo c;
+  ColGeo& c = m.c;
   int xw = x;
   c.real = true;
   if (x < 0 || x >= nx) {
@@ -486,94 +660,30 @@ __global__ __launch_bounds__(256) void fast_kernel(StepParams p, const S* __rest
   c.own = (unsigned)xw;
   c.left = (unsigned)xl;
   c.right = (unsigned)xr;
-  const bool owner = lane >= 1 && lane <= STRIP && x < nx;
+  m.owner = lane >= 1 && lane <= STRIP && x < nx;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int exi = ex(i);
+    m.colB[i] = (exi == 1 ? c.left : (exi == -1 ? c.right : c.own)) * (unsigned)sizeof(S);
+  }
 
   const int y0 = seg * seg_len;
-  const int y1 = min(y0 + seg_len, p.ny);
+  m.y1 = min(y0 + seg_len, p.ny);
 
   double acc[RED_COUNT];
 #pragma unroll
   for (int q = 0; q < RED_COUNT; ++q) acc[q] = 0.0;
 
-  S r0[9], r1[9], r2[9];
-  unsigned off[9];
-  double dr0, jx0, jy0, ps0, dr1, jx1, jy1, ps1, psm;
-  bool bad0, bad1, badm;
+  // Interior strips (lanes x0-1 .. x0+62 with x0-2 >= 0 and x0+63 <= nx-1: no
+  // column wall, no wrap, every lane a node) of y-periodic lattices take the
+  // select-free path; strips at the x edges and y-walled lattices the general one.
+  const int x0 = strip * STRIP;
+  const bool interior = p.periodic_y && x0 >= 2 && x0 + STRIP + 1 <= nx - 1;
+  if (interior)
+    march<S, REDUCE, true>(p, m, y0, acc);
+  else
+    march<S, REDUCE, false>(p, m, y0, acc);
 
-  // prologue: halo row y0-1 (psi only), rows y0 and y0+1 in flight
-  RowGeo gm = row_geo(p, y0 - 1);
-  pull_offsets<S>(gm, c, N, bytes, off);
-  load_row<S>(in, off, r2);
-  RowGeo g0 = row_geo(p, y0);
-  pull_offsets<S>(g0, c, N, bytes, off);
-  load_row<S>(in, off, r0);
-  RowGeo g1 = row_geo(p, y0 + 1);
-  pull_offsets<S>(g1, c, N, bytes, off);
-  load_row<S>(in, off, r1);
-  {
-    double a, bb, cc;
-    row_state<S>(p, r2, gm.real && c.real, a, bb, cc, psm, badm);
-  }
-  row_state<S>(p, r0, g0.real && c.real, dr0, jx0, jy0, ps0, bad0);
-
-  for (int y = y0; y < y1; ++y) {
-    // issue the loads of row y+2 (needed from the next iteration on)
-    RowGeo g2 = row_geo(p, y + 2);
-    if (y + 2 <= y1) {
-      pull_offsets<S>(g2, c, N, bytes, off);
-      load_row<S>(in, off, r2);
-    }
-    // row y+1: density, momentum, psi
-    row_state<S>(p, r1, g1.real && c.real, dr1, jx1, jy1, ps1, bad1);
-    // neighbours' psi (every lane executes the shifts)
-    const double pW = wave_shr1(ps0), pE = wave_shl1(ps0);
-    const double pSW = wave_shr1(psm), pSE = wave_shl1(psm);
-    const double pNW = wave_shr1(ps1), pNE = wave_shl1(ps1);
-    // row y: collide and store
-    double d[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) d[i] = (double)r0[i];
-    double Sx, Sy;
-    stencil_sums(pE, ps1, pW, psm, pNE, pNW, pSW, pSE, Sx, Sy);
-    NodeMacro mac = collide_node(p, d, dr0, jx0, jy0, ps0, Sx, Sy);
-    const bool store = owner && g0.real;
-    const unsigned k = g0.own + c.own;
-#pragma unroll
-    for (int i = 0; i < 9; ++i)
-      BufIO<S>::store((S)d[i], out, store ? ((unsigned)i * N + k) * (unsigned)sizeof(S) : bytes);
-    if (REDUCE && store) {
-      // bounce-back links of this node: the wall received -(f_i + fbar_opp) e_i = -2 f_i e_i
-      double wx = 0.0, wy = 0.0;
-#pragma unroll
-      for (int i = 1; i < 9; ++i) {
-        const int exi = ex(i), eyi = ey(i);
-        const bool wall = (eyi == 1 && g0.wall_b) || (eyi == -1 && g0.wall_t) || (exi == 1 && c.wall_l) ||
-                          (exi == -1 && c.wall_r);
-        if (wall) {
-          double both = 2.0 * ((double)r0[i] + wgt(i) * p.rho_ref);
-          wx -= exi * both;
-          wy -= eyi * both;
-        }
-      }
-      acc[RED_WALLX] += wx;
-      acc[RED_WALLY] += wy;
-      accumulate_node(p, acc, p.rho_ref + dr0, jx0, jy0, mac, bad0);
-    }
-    // rotate the pipeline
-    psm = ps0;
-    ps0 = ps1;
-    dr0 = dr1;
-    jx0 = jx1;
-    jy0 = jy1;
-    bad0 = bad1;
-    g0 = g1;
-    g1 = g2;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      r0[i] = r1[i];
-      r1[i] = r2[i];
-    }
-  }
   if (REDUCE) {
 #pragma unroll
     for (int q = 0; q < RED_COUNT; ++q) {
