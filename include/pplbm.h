@@ -199,6 +199,69 @@ int lbm_state_ptr(const lbm_lattice* h, void** f_dev);
 int lbm_get_state(lbm_lattice* h, void* dst_dev);
 int lbm_set_state(lbm_lattice* h, const void* src_dev, int64_t step);
 
+/* ---------------------------------------------------------------------------
+ * Discrete adjoint (reverse-mode gradients of a loss of a run).
+ *
+ * A run is fbar^0 = f^eq(rho0, 0) (Eq. 7 at rest) followed by n_steps steps.
+ * The observables of step n are those of its pre-collision state (see
+ * lbm_reduction).  Losses:
+ *  LBM_LOSS_DRAG  time-averaged droplet drag over the last W steps (the
+ *                 falling droplet of Sec. 3.3; the paper defines no drag
+ *                 formula, this one is the buoyant weight minus the droplet
+ *                 region's momentum rate):
+ *                   L = (1/W) sum_{n=N-W+1..N} buoy(n) - (pphi(N) - pphi(N-W+1)) / (W - 1)
+ *  LBM_LOSS_UERR  relative squared velocity error of step N (the error norm
+ *                 of Sec. 3.1 without the root):
+ *                   L = sum_fluid (u_x - u_target)^2 / sum_fluid u_target^2
+ * Gradients are those of the discrete run (the adjoint of every step's
+ * streaming, bounce-back, pseudopotential stencil and collision), with respect
+ * to the initial density field, the magnitude |F_ext| of the body force or
+ * gravity (direction held fixed) and the interaction strength G.  They are
+ * computed in double for both precisions; for LBM_FP32_DEV they are those of
+ * the run as stored (the linearisation point is the FP32 trajectory).
+ * Memory: the forward pass saves fbar every checkpoint_every steps; the
+ * backward pass replays each segment from its checkpoint, keeping
+ * rho - rho_ref, j and psi of every step of the segment (32 bytes per node and
+ * step), then runs the reverse steps.  Static solid nodes (mask) are
+ * supported, moving walls (wall_u) are not (LBM_ERR_UNSUPPORTED).
+ * ------------------------------------------------------------------------- */
+
+enum lbm_loss { LBM_LOSS_DRAG = 0, LBM_LOSS_UERR = 1 };
+
+typedef struct lbm_adjoint_cfg {
+  int64_t n_steps;               /* N >= 1 */
+  int64_t window;                /* LBM_LOSS_DRAG: W, 2 <= W <= N (ignored otherwise) */
+  int32_t loss;                  /* enum lbm_loss */
+  int32_t checkpoint_every;      /* K >= 1: steps between saved states */
+  const double* u_target_dev;    /* LBM_LOSS_UERR: [ny][nx] double, device (ignored otherwise) */
+} lbm_adjoint_cfg;
+
+/* Bytes of the adjoint workspace for this lattice and run:
+ * ceil(N/K) + 2 population arrays, min(K, N) * 4 * nx * ny doubles of
+ * trajectory and 23 * nx * ny doubles of adjoint fields (one more for
+ * LBM_LOSS_UERR), plus small reduction buffers.
+ * Pure host computation. */
+int lbm_adjoint_workspace_bytes(const lbm_config* cfg, const lbm_adjoint_cfg* a, size_t* bytes);
+
+/* Forward pass: initialises the lattice at rest with density rho0_dev
+ * ([ny][nx] double, device), runs a->n_steps steps (the handle then holds the
+ * state after step N, as after lbm_step), saves the checkpoints into
+ * workspace_dev (caller-owned, 256-byte aligned, >= lbm_adjoint_workspace_bytes)
+ * and returns the loss in *loss_host.  Keeps a and the workspace pointer for
+ * lbm_adjoint_backward; the caller must keep both (and u_target_dev) alive and
+ * unchanged until then.  Synchronises the stream.  Returns LBM_ERR_EOS_DOMAIN /
+ * LBM_ERR_NONFINITE if a step in the loss window recorded faults (the loss is
+ * still written). */
+int lbm_adjoint_forward(lbm_lattice* h, const lbm_adjoint_cfg* a, const double* rho0_dev, void* workspace_dev,
+                        size_t workspace_bytes, double* loss_host);
+
+/* Reverse pass of the last lbm_adjoint_forward on this handle (LBM_ERR_STATE
+ * if there is none, or if a parameter setter was called since).  Writes
+ * dL/drho0 to grad_rho0_dev ([ny][nx] double, device; 0 at solid nodes) and
+ * dL/d|F_ext|, dL/dG to the host doubles; any output may be NULL.  Does not
+ * change the lattice state; may be called again.  Synchronises the stream. */
+int lbm_adjoint_backward(lbm_lattice* h, double* grad_rho0_dev, double* grad_force_host, double* grad_G_host);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,39 +12,14 @@
 #include <vector>
 
 #include "../../include/pplbm.h"
+#include "lbm_handle.h"
 #include "lbm_internal.h"
 #include "lbm_node.h"
 
 using pplbm::RED_COUNT;
 using pplbm::StepParams;
 
-struct lbm_lattice {
-  lbm_config cfg;
-  lbm_buffers buf;
-  hipStream_t stream;
-  StepParams prm;
-  // user-facing parameters kept to rebuild prm
-  double s[9];
-  int scheme;
-  double eps, k1, k2;
-  int q2_policy;
-  double rho_s;
-  int cur = 0;  // 0: f_a holds the current state, 1: f_b
-  int64_t steps = 0;
-  bool initialized = false;
-  int seg_len = 64;
-  // workspace carve-up
-  double* partials = nullptr;
-  size_t max_parts = 0;
-  double* log = nullptr;
-  double* red_tmp = nullptr;
-  void* psi = nullptr;
-  std::string err;
-};
-
-namespace {
-
-std::string g_create_error;
+namespace pplbm_host {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -58,6 +33,40 @@ int fail(lbm_lattice* h, int code, const std::string& msg) {
 int hip_fail(lbm_lattice* h, hipError_t e, const char* what) {
   return fail(h, LBM_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
+
+// The specialised strip kernel handles lattices without a mask or moving walls
+// whose population arrays fit 32-bit byte offsets.
+bool fast_path(const lbm_lattice* h) {
+  double bytes = 9.0 * (double)h->cfg.nx * (double)h->cfg.ny * (double)elem_size(&h->cfg);
+  return h->cfg.kernel == LBM_KERNEL_FUSED && !h->buf.mask && !h->buf.wall_u && bytes < 4294967040.0;
+}
+
+hipError_t step_between(lbm_lattice* h, const void* f_in, void* f_out, int reduce) {
+  pplbm::StepLaunch L;
+  L.f_in = f_in;
+  L.f_out = f_out;
+  L.mask = h->buf.mask;
+  L.wall_u = h->buf.wall_u;
+  L.psi = h->psi;
+  L.partials = h->partials;
+  L.kernel = h->cfg.kernel;
+  L.seg_len = h->seg_len;
+  L.reduce = reduce;
+  L.fast = fast_path(h) ? 1 : 0;
+  return (h->cfg.precision == LBM_FP64) ? pplbm::launch_step<double>(h->prm, L, h->stream)
+                                        : pplbm::launch_step<float>(h->prm, L, h->stream);
+}
+
+int n_parts_of(const lbm_lattice* h) {
+  if (h->cfg.kernel == LBM_KERNEL_TWO_PASS) return pplbm::two_pass_blocks(h->cfg.nx, h->cfg.ny);
+  int n_strips, n_segs;
+  pplbm::fused_shape(h->cfg.nx, h->cfg.ny, h->seg_len, &n_strips, &n_segs);
+  return n_strips * n_segs;
+}
+
+void* state_ptr(lbm_lattice* h, int which) { return which == 0 ? h->buf.f_a : h->buf.f_b; }
+
+std::string g_create_error;
 
 bool config_ok(const lbm_config* c, std::string& why) {
   if (!c) {
@@ -130,6 +139,7 @@ Layout layout_for(const lbm_config* c) {
 }
 
 void rebuild_params(lbm_lattice* h) {
+  h->adj.ready = false;
   StepParams& p = h->prm;
   for (int k = 0; k < 9; ++k) {
     p.s[k] = h->s[k];
@@ -162,37 +172,7 @@ bool all_finite(std::initializer_list<double> v) {
   return true;
 }
 
-void* state_ptr(lbm_lattice* h, int which) { return which == 0 ? h->buf.f_a : h->buf.f_b; }
 
-// The specialised strip kernel handles lattices without a mask or moving walls
-// whose population arrays fit 32-bit byte offsets.
-bool fast_path(const lbm_lattice* h) {
-  double bytes = 9.0 * (double)h->cfg.nx * (double)h->cfg.ny * (double)elem_size(&h->cfg);
-  return h->cfg.kernel == LBM_KERNEL_FUSED && !h->buf.mask && !h->buf.wall_u && bytes < 4294967040.0;
-}
-
-template <class T>
-hipError_t step_one(lbm_lattice* h, int reduce) {
-  pplbm::StepLaunch L;
-  L.f_in = state_ptr(h, h->cur);
-  L.f_out = state_ptr(h, 1 - h->cur);
-  L.mask = h->buf.mask;
-  L.wall_u = h->buf.wall_u;
-  L.psi = h->psi;
-  L.partials = h->partials;
-  L.kernel = h->cfg.kernel;
-  L.seg_len = h->seg_len;
-  L.reduce = reduce;
-  L.fast = fast_path(h) ? 1 : 0;
-  return pplbm::launch_step<T>(h->prm, L, h->stream);
-}
-
-int n_parts_of(lbm_lattice* h) {
-  if (h->cfg.kernel == LBM_KERNEL_TWO_PASS) return pplbm::two_pass_blocks(h->cfg.nx, h->cfg.ny);
-  int n_strips, n_segs;
-  pplbm::fused_shape(h->cfg.nx, h->cfg.ny, h->seg_len, &n_strips, &n_segs);
-  return n_strips * n_segs;
-}
 
 void fill_record(const double* v, int64_t step, lbm_reduction* r) {
   r->mass = v[pplbm::RED_MASS];
@@ -218,7 +198,9 @@ int fault_status(lbm_lattice* h, const lbm_reduction& r) {
   return LBM_OK;
 }
 
-}  // namespace
+}  // namespace pplbm_host
+
+using namespace pplbm_host;
 
 extern "C" {
 
@@ -415,7 +397,7 @@ int lbm_step(lbm_lattice* h, int64_t n, int32_t reduce_every, lbm_reduction* out
   for (int64_t t = 0; t < n; ++t) {
     int64_t idx = h->steps + 1;
     int reduce = (reduce_every > 0 && idx % reduce_every == 0) ? 1 : 0;
-    hipError_t e = (h->cfg.precision == LBM_FP64) ? step_one<double>(h, reduce) : step_one<float>(h, reduce);
+    hipError_t e = step_between(h, state_ptr(h, h->cur), state_ptr(h, 1 - h->cur), reduce);
     if (e != hipSuccess) return hip_fail(h, e, "step launch");
     if (reduce) {
       e = pplbm::launch_finalize(h->partials, parts, h->log + rec_steps.size() * RED_COUNT, h->stream);

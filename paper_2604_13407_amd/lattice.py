@@ -27,6 +27,7 @@ EOS_VDW, EOS_CS = 0, 1
 SCHEME_ORIGINAL, SCHEME_IMPROVED = 0, 1
 Q2_DEFAULT, Q2_NEG_Q1, Q2_NEG_HALF_Q1 = 0, 1, 2
 FORCE_CONST, FORCE_BUOYANT = 0, 1
+LOSS_DRAG, LOSS_UERR = 0, 1
 
 RED_FIELDS = ("mass", "mom_x", "mom_y", "wall_x", "wall_y", "uc_num", "uc_den", "buoy", "pphi", "faults")
 
@@ -35,7 +36,8 @@ EXPORTS = ("lbm_abi_version", "lbm_state_bytes", "lbm_workspace_bytes", "lbm_cre
            "lbm_last_error", "lbm_set_eos", "lbm_set_G", "lbm_set_relaxation", "lbm_set_scheme",
            "lbm_set_body_force", "lbm_set_phase_densities", "lbm_set_walls", "lbm_init_equilibrium", "lbm_step",
            "lbm_set_rows_per_wave",
-           "lbm_step_count", "lbm_read_fields", "lbm_reduce", "lbm_state_ptr", "lbm_get_state", "lbm_set_state")
+           "lbm_step_count", "lbm_read_fields", "lbm_reduce", "lbm_state_ptr", "lbm_get_state", "lbm_set_state",
+           "lbm_adjoint_workspace_bytes", "lbm_adjoint_forward", "lbm_adjoint_backward")
 
 
 class LbmError(RuntimeError):
@@ -62,6 +64,11 @@ class Reduction(C.Structure):
         d = {n: getattr(self, n) for n in RED_FIELDS}
         d["step"] = int(self.step)
         return d
+
+
+class AdjointConfig(C.Structure):
+    _fields_ = [("n_steps", C.c_int64), ("window", C.c_int64), ("loss", C.c_int32), ("checkpoint_every", C.c_int32),
+                ("u_target_dev", C.c_void_p)]
 
 
 _lib = None
@@ -98,6 +105,9 @@ def lib():
         L.lbm_state_ptr.argtypes = [vp, C.POINTER(vp)]
         L.lbm_get_state.argtypes = [vp, vp]
         L.lbm_set_state.argtypes = [vp, vp, C.c_int64]
+        L.lbm_adjoint_workspace_bytes.argtypes = [C.POINTER(Config), C.POINTER(AdjointConfig), C.POINTER(C.c_size_t)]
+        L.lbm_adjoint_forward.argtypes = [vp, C.POINTER(AdjointConfig), vp, vp, C.c_size_t, dp]
+        L.lbm_adjoint_backward.argtypes = [vp, vp, dp, dp]
         _lib = L
     return _lib
 
@@ -184,6 +194,15 @@ class Lattice:
 
     def set_body_force(self, mode: int, fx: float, fy: float):
         self._check(lib().lbm_set_body_force(self.h, mode, fx, fy), self.h)
+        self.force = (mode, float(fx), float(fy))
+
+    def set_force_magnitude(self, mag: float):
+        """Rescales the body force / gravity to magnitude mag, keeping its mode and direction."""
+        mode, fx, fy = self.force
+        n = math.hypot(fx, fy)
+        if n == 0.0:
+            raise ValueError("the body force has no direction to rescale")
+        self.set_body_force(mode, fx * mag / n, fy * mag / n)
 
     def set_phase_densities(self, rho_g: float, rho_l: float):
         self._check(lib().lbm_set_phase_densities(self.h, rho_g, rho_l), self.h)
@@ -248,6 +267,41 @@ class Lattice:
         r = Reduction()
         self._check(lib().lbm_reduce(self.h, C.byref(r)), self.h)
         return r.as_dict()
+
+    # ------------------------------------------------------------ adjoint
+    def adjoint_forward(self, rho0, n_steps: int, loss: int = LOSS_DRAG, window: int = 2,
+                        checkpoint_every: int = 100, u_target=None) -> float:
+        """Runs n_steps from rest with density rho0, saving checkpoints, and returns the loss
+        (LOSS_DRAG over the last `window` steps, or LOSS_UERR against u_target).  The lattice
+        then holds the state after the run; adjoint_backward() gives the gradients."""
+        r = _dev(rho0, self.device, torch.float64)
+        assert tuple(r.shape) == (self.ny, self.nx)
+        ut = _dev(u_target, self.device, torch.float64)
+        if loss == LOSS_UERR:
+            assert ut is not None and tuple(ut.shape) == (self.ny, self.nx)
+        acfg = AdjointConfig(int(n_steps), int(window), int(loss), int(checkpoint_every),
+                             None if ut is None else ut.data_ptr())
+        nb = C.c_size_t(0)
+        self._check(lib().lbm_adjoint_workspace_bytes(C.byref(self.cfg), C.byref(acfg), C.byref(nb)), self.h)
+        ws = getattr(self, "_adj_ws", None)
+        if ws is None or ws.numel() < nb.value:
+            self._adj_ws = None
+            ws = self._adj_ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        assert ws.data_ptr() % 256 == 0
+        out = C.c_double(0.0)
+        # the library keeps acfg's contents and u_target's pointer for adjoint_backward
+        self._adj_keep = (r, ut, acfg)
+        self._check(lib().lbm_adjoint_forward(self.h, C.byref(acfg), _ptr(r), _ptr(ws), ws.numel(), C.byref(out)),
+                    self.h)
+        return out.value
+
+    def adjoint_backward(self):
+        """Gradients of the last adjoint_forward's loss: (dL/drho0 [ny, nx] FP64 device tensor,
+        dL/d|F_ext|, dL/dG)."""
+        g = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+        gf, gG = C.c_double(0.0), C.c_double(0.0)
+        self._check(lib().lbm_adjoint_backward(self.h, _ptr(g), C.byref(gf), C.byref(gG)), self.h)
+        return g, gf.value, gG.value
 
     # ------------------------------------------------------------ convenience
     @classmethod

@@ -104,3 +104,63 @@ def test_no_cpu_fallback_without_a_gpu():
         pytest.skip("a GPU is present")
     with pytest.raises(RuntimeError):
         LT.Lattice(8, 8)
+
+
+def acfg(**kw):
+    base = dict(n_steps=100, window=10, loss=LT.LOSS_DRAG, checkpoint_every=30, u_target_dev=None)
+    base.update(kw)
+    return LT.AdjointConfig(**base)
+
+
+def test_adjoint_workspace_size_and_validation():
+    L = LT.lib()
+    b = C.c_size_t(0)
+    c = cfg()
+    n = 64 * 32
+    assert L.lbm_adjoint_workspace_bytes(C.byref(c), C.byref(acfg()), C.byref(b)) == 0
+    # 4 checkpoints (steps 0, 30, 60, 90) + 2 replay arrays of FP32 populations, 30 trajectory
+    # slots of 4 doubles, 23 doubles of adjoint fields per node
+    assert b.value >= (4 + 2) * 9 * n * 4 + 30 * 4 * n * 8 + 23 * n * 8
+    assert b.value % 256 == 0
+    small = b.value
+    assert L.lbm_adjoint_workspace_bytes(C.byref(c), C.byref(acfg(checkpoint_every=10)), C.byref(b)) == 0
+    assert b.value < small  # fewer trajectory slots outweigh the extra checkpoints here
+    assert L.lbm_adjoint_workspace_bytes(C.byref(c), C.byref(acfg(checkpoint_every=1000)), C.byref(b)) == 0
+    assert b.value >= 100 * 4 * n * 8  # trajectory slots are capped at n_steps
+    for bad in (dict(n_steps=0), dict(checkpoint_every=0), dict(window=1), dict(window=101), dict(loss=7),
+                dict(loss=LT.LOSS_UERR)):
+        assert L.lbm_adjoint_workspace_bytes(C.byref(c), C.byref(acfg(**bad)), C.byref(b)) == -1, bad
+    assert L.lbm_adjoint_workspace_bytes(C.byref(c), C.byref(acfg(loss=LT.LOSS_UERR, u_target_dev=0x1000)),
+                                         C.byref(b)) == 0
+
+
+def test_adjoint_argument_and_state_errors_without_a_gpu():
+    L, h = fake_handle()
+    try:
+        gf, gG = C.c_double(0), C.c_double(0)
+        assert L.lbm_adjoint_backward(h, None, C.byref(gf), C.byref(gG)) == -6
+        out = C.c_double(0)
+        a = acfg(window=1)
+        assert L.lbm_adjoint_forward(h, C.byref(a), C.c_void_p(0x4000), C.c_void_p(0x8000), 1 << 30,
+                                     C.byref(out)) == -1
+        a = acfg()
+        assert L.lbm_adjoint_forward(h, C.byref(a), None, C.c_void_p(0x8000), 1 << 30, C.byref(out)) == -1
+        assert L.lbm_adjoint_forward(h, C.byref(a), C.c_void_p(0x4000), C.c_void_p(0x8001), 1 << 30,
+                                     C.byref(out)) == -1
+        assert L.lbm_adjoint_forward(h, C.byref(a), C.c_void_p(0x4000), C.c_void_p(0x8000), 256,
+                                     C.byref(out)) == -1
+        assert "too small" in L.lbm_last_error(h).decode()
+        assert L.lbm_adjoint_backward(h, None, None, None) == -6
+    finally:
+        L.lbm_destroy(h)
+    # moving walls are not supported by the adjoint
+    c = cfg()
+    buf = LT.Buffers(0x10000, 0x20000, 0x30000, None, 0x40000)
+    h = C.c_void_p(0)
+    assert L.lbm_create(C.byref(c), C.byref(buf), None, C.byref(h)) == 0
+    try:
+        out = C.c_double(0)
+        assert L.lbm_adjoint_forward(h, C.byref(acfg()), C.c_void_p(0x4000), C.c_void_p(0x8000), 1 << 30,
+                                     C.byref(out)) == -5
+    finally:
+        L.lbm_destroy(h)
