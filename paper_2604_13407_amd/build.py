@@ -22,6 +22,9 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions in generated device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # contraction of a*b+c into FMA only within one expression (as written), so that the
+    # rounding of the step does not depend on how the optimiser shares or places code
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-result",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
