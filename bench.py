@@ -51,6 +51,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="time only the FP32 headline path")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--adjoint-only", action="store_true", help="time only the adjoint (profiling)")
+    ap.add_argument("--adjoint-steps", type=int, default=0,
+                    help="steps of the adjoint run (default: the workload's 20,000)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for HBM counter scaling)")
     return ap.parse_args()
@@ -79,6 +83,45 @@ def gpu_run(w, precision, steps, warmup, reduce_every):
     ms, wall = time_steps(lat, steps, reduce_every)
     rec = lat.reduce()
     out = {"ms_per_step": ms / steps, "wall_s": wall, "mass": rec["mass"], "faults": rec["faults"]}
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
+def adjoint_run(n_steps=0):
+    """Falling-droplet adjoint, 512 x 2048, FP32 storage: the plain forward run, the
+    checkpointed forward (checkpoints every 500 steps, drag loss over the last 5,000
+    steps) and the reverse sweep, each timed on the host around its synchronising call."""
+    import torch
+    from paper_2604_13407_amd import lattice as LT
+    from paper_2604_13407_amd import workloads as WL
+    w = WL.droplet_adjoint()
+    n = n_steps or w.steps
+    window, K = max(2, n // 4), 500
+    lat = LT.Lattice.from_workload(w, precision=LT.FP32_DEV, init=False)
+    rho0 = torch.tensor(w.rho0(), dtype=torch.float64, device=lat.device)
+    lat.init_equilibrium(rho0)
+    lat.step(20)  # warm-up (kernel loading)
+    lat.init_equilibrium(rho0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(n)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    loss = lat.adjoint_forward(rho0, n, loss=LT.LOSS_DRAG, window=window, checkpoint_every=K)
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    g, g_force, g_G = lat.adjoint_backward()
+    t_bwd = time.perf_counter() - t0
+    ws_gb = lat._adj_ws.numel() / 1e9
+    out = {"workload": f"droplet adjoint {w.nx}x{w.ny}, R=64, {n} steps, checkpoint every {K}, "
+                       f"drag over the last {window} steps, FP32 storage",
+           "plain_forward_s": round(t_plain, 4), "forward_s": round(t_fwd, 4), "backward_s": round(t_bwd, 4),
+           "backward_over_forward": round(t_bwd / t_fwd, 3), "gradient_over_plain_run": round((t_fwd + t_bwd) / t_plain, 3),
+           "forward_MLUPS": round(w.nodes * n / t_fwd / 1e6, 1), "backward_MLUPS": round(w.nodes * n / t_bwd / 1e6, 1),
+           "workspace_GB": round(ws_gb, 2), "loss": loss, "dL_dg": g_force, "dL_dG": g_G,
+           "dL_drho0_norm": float(g.norm())}
     del lat
     torch.cuda.empty_cache()
     return out
@@ -137,6 +180,9 @@ def main():
     w = WL.droplet()
     reduce_every = w.reduce_every
     steps, warmup = args.steps, args.warmup
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_run(args.adjoint_steps)}), flush=True)
+        return
 
     head = gpu_run(w, LT.FP32_DEV, steps, warmup, reduce_every)
     ms = head["ms_per_step"]
@@ -182,6 +228,9 @@ def main():
         orig = gpu_run(WL.droplet(scheme=WL.SCHEME_ORIGINAL), LT.FP32_DEV, steps, warmup, reduce_every)
         result["original_scheme"] = {"value": round(w.nodes / (orig["ms_per_step"] * 1e-3) / 1e6, 1),
                                      "unit": "MLUPS", "ms_per_step": round(orig["ms_per_step"], 5)}
+
+    if not args.no_adjoint:
+        result["adjoint"] = adjoint_run(args.adjoint_steps)
 
     if args.copy_calibration:
         result["copy_calibration"] = copy_calibration()

@@ -22,9 +22,12 @@
 //     inverted); the user's G multiplies Eq. (4) and the G psi^2 of Eqs. (11),
 //     (13), (42).  With G = -1 this is exactly the paper's model.
 //
-// The scalar type is a template parameter: T = double for ordinary runs and
-// T = std::complex<double> for complex-step derivatives.  Every branch tests
-// the real part, so the complex run follows the same path as the real one.
+// The scalar type is a template parameter: T = double for ordinary runs,
+// T = std::complex<double> for complex-step derivatives, and T = Rv, a
+// reverse-mode scalar that records every operation on a tape, for the
+// oracle's own discrete adjoint (the transpose of the same arithmetic,
+// obtained mechanically by sweeping the tape backwards).  Every branch tests
+// the real part, so all three follow the same path.
 //
 // Build: g++ -O2 -std=c++17 -ffp-contract=off -fopenmp -shared -fPIC
 // (no fast-math; IEEE binary64 round-to-nearest everywhere).
@@ -33,6 +36,7 @@
 #include <complex>
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 #ifdef _OPENMP
 #include <omp.h>
@@ -48,6 +52,81 @@ inline double im(double) { return 0.0; }
 inline double im(const cplx& v) { return v.imag(); }
 inline bool finite_value(double v) { return std::isfinite(v); }
 inline bool finite_value(const cplx& v) { return std::isfinite(v.real()) && std::isfinite(v.imag()); }
+
+// ---------------------------------------------------------------- reverse mode
+// The tape: node t was produced from operands a[t], b[t] (-1: none) with
+// partial derivatives da[t], db[t].  Inputs are nodes without operands.
+struct Tape {
+  std::vector<int64_t> a, b;
+  std::vector<double> da, db;
+  int64_t push(int64_t ia, double pa, int64_t ib, double pb) {
+    a.push_back(ia);
+    da.push_back(pa);
+    b.push_back(ib);
+    db.push_back(pb);
+    return (int64_t)a.size() - 1;
+  }
+  // Adjoints of every node given a seed of 1 at `out`.
+  std::vector<double> reverse(int64_t out) const {
+    std::vector<double> adj(a.size(), 0.0);
+    if (out < 0) return adj;
+    adj[out] = 1.0;
+    for (int64_t t = out; t >= 0; --t) {
+      const double g = adj[t];
+      if (g == 0.0) continue;
+      if (a[t] >= 0) adj[a[t]] += da[t] * g;
+      if (b[t] >= 0) adj[b[t]] += db[t] * g;
+    }
+    return adj;
+  }
+};
+
+Tape* g_tape = nullptr;  // the tape being recorded (one at a time, single-threaded)
+
+// A value and its tape node (-1 for a constant, which records nothing).
+struct Rv {
+  double v = 0.0;
+  int64_t id = -1;
+  Rv() = default;
+  Rv(double x) : v(x), id(-1) {}
+  static Rv input(double x) {
+    Rv r(x);
+    r.id = g_tape->push(-1, 0.0, -1, 0.0);
+    return r;
+  }
+  static Rv node(double val, int64_t ia, double pa, int64_t ib, double pb) {
+    Rv r(val);
+    if (ia >= 0 || ib >= 0) r.id = g_tape->push(ia, pa, ib, pb);
+    return r;
+  }
+  Rv& operator+=(const Rv& o);
+  Rv& operator-=(const Rv& o);
+};
+inline Rv operator+(const Rv& x, const Rv& y) { return Rv::node(x.v + y.v, x.id, 1.0, y.id, 1.0); }
+inline Rv operator-(const Rv& x, const Rv& y) { return Rv::node(x.v - y.v, x.id, 1.0, y.id, -1.0); }
+inline Rv operator*(const Rv& x, const Rv& y) { return Rv::node(x.v * y.v, x.id, y.v, y.id, x.v); }
+inline Rv operator/(const Rv& x, const Rv& y) {
+  const double q = x.v / y.v;
+  return Rv::node(q, x.id, 1.0 / y.v, y.id, -q / y.v);
+}
+inline Rv operator-(const Rv& x) { return Rv::node(-x.v, x.id, -1.0, -1, 0.0); }
+inline Rv operator+(const Rv& x, double y) { return x + Rv(y); }
+inline Rv operator+(double x, const Rv& y) { return Rv(x) + y; }
+inline Rv operator-(const Rv& x, double y) { return x - Rv(y); }
+inline Rv operator-(double x, const Rv& y) { return Rv(x) - y; }
+inline Rv operator*(const Rv& x, double y) { return x * Rv(y); }
+inline Rv operator*(double x, const Rv& y) { return Rv(x) * y; }
+inline Rv operator/(const Rv& x, double y) { return x / Rv(y); }
+inline Rv operator/(double x, const Rv& y) { return Rv(x) / y; }
+inline Rv& Rv::operator+=(const Rv& o) { return *this = *this + o; }
+inline Rv& Rv::operator-=(const Rv& o) { return *this = *this - o; }
+// d sqrt(q) = dq / (2 sqrt(q)); taken as 0 at q = 0 (a clamped pseudopotential).
+inline Rv sqrt(const Rv& q) {
+  const double r = std::sqrt(q.v);
+  return Rv::node(r, q.id, r > 0.0 ? 0.5 / r : 0.0, -1, 0.0);
+}
+inline double re(const Rv& v) { return v.v; }
+inline bool finite_value(const Rv& v) { return std::isfinite(v.v); }
 
 // D2Q9 lattice (Sec. 2; velocity order as listed in the header comment).
 const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -201,7 +280,8 @@ struct Sim {
       fault = 1;
       psi2 = T(0);
     }
-    return std::sqrt(psi2);
+    using std::sqrt;
+    return sqrt(psi2);
   }
 
   void init_equilibrium(const T* rho0, const double* ux0, const double* uy0) {
@@ -313,7 +393,7 @@ struct Sim {
       int fl = 0;
       psi_solid_value = psi_of(T(p.rho_s), fl);
     }
-#pragma omp parallel for schedule(static) reduction(+ : faults)
+#pragma omp parallel for schedule(static) reduction(+ : faults) if (kParallel)
     for (int y = 0; y < ny; ++y) {
       for (int x = 0; x < nx; ++x) {
         size_t k = idx(x, y);
@@ -360,7 +440,7 @@ struct Sim {
       if (solid[k]) psi[k] = psi_solid_value;
 
     // S4: interaction force, Eq. (4), total force and velocity, Eq. (3).
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (kParallel)
     for (int y = 0; y < ny; ++y) {
       for (int x = 0; x < nx; ++x) {
         size_t k = idx(x, y);
@@ -395,7 +475,8 @@ struct Sim {
 
   void reductions(T* red, int faults) {
     for (int q = 0; q < RED_COUNT; ++q) red[q] = T(0);
-    T gmag = std::sqrt(fx * fx + fy * fy);
+    using std::sqrt;
+    T gmag = sqrt(fx * fx + fy * fy);
     T ghx = T(0), ghy = T(0);
     if (re(gmag) > 0.0) {
       ghx = fx / gmag;
@@ -436,7 +517,7 @@ struct Sim {
   int step(T* red) {
     int faults = macroscopic(red);
     std::vector<T> fnew(f);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (kParallel)
     for (int y = 0; y < ny; ++y) {
       for (int x = 0; x < nx; ++x) {
         size_t k = idx(x, y);
@@ -452,7 +533,41 @@ struct Sim {
   }
 
   T psi_solid_value = T(0);
+  // Recording a tape is sequential.
+  static constexpr bool kParallel = !std::is_same<T, Rv>::value;
 };
+
+// The loss of a run of nsteps from the current state (see oracle_loss).
+template <class T>
+T run_loss(Sim<T>& s, const OracleLoss* loss, int64_t nsteps) {
+  std::vector<T> red(RED_COUNT);
+  T L(0.0);
+  T p_first(0.0), p_last(0.0);
+  for (int64_t t = 1; t <= nsteps; ++t) {
+    bool last = (t == nsteps);
+    bool in_window = (loss->kind == 0) && (t > nsteps - loss->window);
+    if (in_window || (loss->kind == 1 && last)) {
+      s.macroscopic(red.data());
+      if (loss->kind == 0) {
+        L += red[RED_BUOY] / double(loss->window);
+        if (t == nsteps - loss->window + 1) p_first = red[RED_PPHI];
+        if (last) p_last = red[RED_PPHI];
+      } else {
+        T num(0.0), den(0.0);
+        for (size_t k = 0; k < s.n; ++k) {
+          if (s.solid[k]) continue;
+          T d = s.ux[k] - loss->u_target[k];
+          num += d * d;
+          den += loss->u_target[k] * loss->u_target[k];
+        }
+        L = num / den;
+      }
+    }
+    s.step(nullptr);
+  }
+  if (loss->kind == 0) L -= (p_last - p_first) / double(loss->window - 1);
+  return L;
+}
 
 int set_threads(int nthreads) {
 #ifdef _OPENMP
@@ -585,34 +700,48 @@ int oracle_loss(const OracleParams* p, const uint8_t* mask, const double* wall_u
   for (size_t k = 0; k < s.n; ++k) r0[k] = cplx(rho0[k]) + ((perturb == 3) ? ih * v[k] : cplx(0.0));
   s.init_equilibrium(r0.data(), nullptr, nullptr);
 
-  std::vector<cplx> red(RED_COUNT);
-  cplx L(0.0);
-  cplx p_first(0.0), p_last(0.0);
-  for (int64_t t = 1; t <= nsteps; ++t) {
-    bool last = (t == nsteps);
-    bool in_window = (loss->kind == 0) && (t > nsteps - loss->window);
-    if (in_window || (loss->kind == 1 && last)) {
-      s.macroscopic(red.data());
-      if (loss->kind == 0) {
-        L += red[RED_BUOY] / double(loss->window);
-        if (t == nsteps - loss->window + 1) p_first = red[RED_PPHI];
-        if (last) p_last = red[RED_PPHI];
-      } else {
-        cplx num(0.0), den(0.0);
-        for (size_t k = 0; k < s.n; ++k) {
-          if (s.solid[k]) continue;
-          cplx d = s.ux[k] - loss->u_target[k];
-          num += d * d;
-          den += loss->u_target[k] * loss->u_target[k];
-        }
-        L = num / den;
-      }
-    }
-    s.step(nullptr);
-  }
-  if (loss->kind == 0) L -= (p_last - p_first) / double(loss->window - 1);
+  cplx L = run_loss(s, loss, nsteps);
   if (L_out) *L_out = re(L);
   if (dL_out) *dL_out = (perturb != 0 && h != 0.0) ? im(L) / h : 0.0;
+  return 0;
+}
+
+// The oracle's own discrete adjoint of the same loss: the run is recorded on a
+// tape in the reverse-mode scalar and swept backwards once.  Outputs (any may
+// be null): the loss, dL/drho0 at every node (ny*nx; 0 at solid nodes), dL/dG
+// and dL/d|F| (body force or gravity magnitude, direction fixed).  Runs on one
+// thread; the tape holds roughly 1,000 entries (32 bytes each) per node and
+// step, so it is meant for small lattices.  Returns -1 on bad arguments, -2
+// when the tape would exceed max_tape entries.
+int oracle_adjoint(const OracleParams* p, const uint8_t* mask, const double* wall_u, const double* rho0,
+                   int64_t nsteps, const OracleLoss* loss, int64_t max_tape, double* L_out, double* grad_rho0,
+                   double* dG_out, double* dF_out) {
+  if (!params_ok(p) || !rho0 || !loss || nsteps < 1) return -1;
+  if (loss->kind == 0 && (loss->window < 2 || loss->window > nsteps)) return -1;
+  if (loss->kind == 1 && !loss->u_target) return -1;
+  const size_t n = (size_t)p->nx * p->ny;
+  if ((double)n * (double)nsteps * 1000.0 > (double)max_tape) return -2;
+  Tape tape;
+  g_tape = &tape;
+  Sim<Rv> s(*p, mask, wall_u);
+  s.G = Rv::input(p->G);
+  const double mag = std::sqrt(p->fx * p->fx + p->fy * p->fy);
+  Rv F = Rv::input(mag);
+  if (mag > 0.0) {
+    s.fx = F * (p->fx / mag);
+    s.fy = F * (p->fy / mag);
+  }
+  std::vector<Rv> r0(n);
+  for (size_t k = 0; k < n; ++k) r0[k] = Rv::input(rho0[k]);
+  s.init_equilibrium(r0.data(), nullptr, nullptr);
+  Rv L = run_loss(s, loss, nsteps);
+  g_tape = nullptr;
+  std::vector<double> adj = tape.reverse(L.id);
+  if (L_out) *L_out = L.v;
+  if (grad_rho0)
+    for (size_t k = 0; k < n; ++k) grad_rho0[k] = s.solid[k] ? 0.0 : adj[r0[k].id];
+  if (dG_out) *dG_out = adj[s.G.id];
+  if (dF_out) *dF_out = adj[F.id];
   return 0;
 }
 

@@ -135,6 +135,7 @@ def lib():
         L.oracle_psi.restype = C.c_double
         L.oracle_loss.argtypes = [pp, u8, dp, dp, C.c_int64, C.POINTER(_Loss), C.c_int32, dp, C.c_double,
                                   dp, dp, C.c_int]
+        L.oracle_adjoint.argtypes = [pp, u8, dp, dp, C.c_int64, C.POINTER(_Loss), C.c_int64, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -295,3 +296,26 @@ def loss(params: Params, rho0, nsteps: int, kind: int, window: int = 2, u_target
                            _dp(v), float(h), C.byref(L), C.byref(dL), int(threads))
     assert rc == 0, rc
     return L.value, dL.value
+
+
+def adjoint(params: Params, rho0, nsteps: int, kind: int, window: int = 2, u_target=None, mask=None,
+            wall_u=None, max_tape: int = 60_000_000):
+    """The oracle's own discrete adjoint of the loss (reverse sweep of a recorded tape).
+    Returns (L, dL/drho0 [ny, nx], dL/dG, dL/d|F|).  Small lattices only: the tape holds
+    about 1,000 entries per node and step."""
+    shp = (params.ny, params.nx)
+    rho0 = _f64(rho0, shp)
+    mask = _mask(mask, shp)
+    wall_u = _f64(wall_u, (2,) + shp)
+    ut = _f64(u_target, shp)
+    spec = _Loss()
+    spec.kind = kind
+    spec.window = window
+    spec.u_target = _dp(ut)
+    L, dG, dF = C.c_double(0.0), C.c_double(0.0), C.c_double(0.0)
+    g = np.zeros(shp)
+    p = params.to_c()
+    rc = lib().oracle_adjoint(C.byref(p), _u8(mask), _dp(wall_u), _dp(rho0), int(nsteps), C.byref(spec),
+                              int(max_tape), C.byref(L), _dp(g), C.byref(dG), C.byref(dF))
+    assert rc == 0, rc
+    return L.value, g, dG.value, dF.value

@@ -1,7 +1,8 @@
 """GPU discrete adjoint (through the C-ABI) against the FP64 oracle.
 
 The oracle's derivatives are complex-step tangents of its own run (exact to
-rounding for these analytic steps).  Bars: the FP64 GPU gradients within
+rounding for these analytic steps) and its own discrete adjoint (a reverse
+sweep of its recorded run, which gives the whole dL/drho0 field).  Bars: the FP64 GPU gradients within
 1e-9 relative of them, the FP32-storage gradients within 1e-3.  At the full
 falling-droplet adjoint size (512 x 2048, 20,000 steps, checkpoints every 500)
 the oracle is too slow; there the GPU gradients are checked against central
@@ -104,6 +105,21 @@ def test_fp64_adjoint_matches_oracle_complex_step(name, oracle_small):
         assert rel(float((g * v).sum()), d) <= 1e-9, (float((g * v).sum()), d)
     if mask is not None:
         assert np.all(g[mask == 1] == 0.0)
+
+
+@pytest.mark.parametrize("name", ("drag", "masked_uerr"))
+@pytest.mark.parametrize("precision", (LT.FP64, LT.FP32_DEV))
+def test_gradient_field_matches_the_oracle_adjoint(name, precision):
+    """dL/drho0 node by node, dL/dG and dL/d|F| against the oracle's own discrete adjoint
+    (a reverse sweep of its recorded run)."""
+    w, mask, kind, ut = small_case(name)
+    Lo, go, dGo, dFo = O.adjoint(oracle_params(w), w.rho0(), N_SMALL, kind, window=W_SMALL, u_target=ut, mask=mask)
+    L, gG, gf, g, _ = gpu_gradients(w, mask, kind, ut, N_SMALL, W_SMALL, K_SMALL, precision=precision)
+    tol = 1e-9 if precision == LT.FP64 else 1e-3
+    err = np.max(np.abs(g - go)) / np.max(np.abs(go))
+    print(f"{name} {precision}: field err {err:.2e} dG {rel(gG, dGo):.2e} dF {rel(gf, dFo):.2e}", flush=True)
+    assert err <= tol
+    assert rel(gG, dGo) <= tol and rel(gf, dFo) <= tol
 
 
 @pytest.mark.parametrize("name", ("drag", "uerr", "masked_drag"))
