@@ -127,7 +127,7 @@ def adjoint_run(n_steps=0):
     return out
 
 
-def cpu_baseline(w, target_s=12.0):
+def cpu_baseline(w, target_s=20.0):
     """The FP64 oracle on a band of the same lattice (full width, 512 rows
     through the droplet), as many steps as fit in about target_s seconds."""
     import numpy as np
