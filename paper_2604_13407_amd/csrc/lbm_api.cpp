@@ -60,7 +60,8 @@ hipError_t step_between(lbm_lattice* h, const void* f_in, void* f_out, int reduc
 int n_parts_of(const lbm_lattice* h) {
   if (h->cfg.kernel == LBM_KERNEL_TWO_PASS) return pplbm::two_pass_blocks(h->cfg.nx, h->cfg.ny);
   int n_strips, n_segs;
-  pplbm::fused_shape(h->cfg.nx, h->cfg.ny, h->seg_len, &n_strips, &n_segs);
+  pplbm::fused_shape(h->cfg.nx, h->cfg.ny, h->seg_len, pplbm::aligned_strips(h->cfg.nx, fast_path(h) ? 1 : 0),
+                     &n_strips, &n_segs);
   return n_strips * n_segs;
 }
 
@@ -113,7 +114,7 @@ int default_seg_len(int nx, int ny) {
 
 size_t max_parts_for(const lbm_config* c) {
   int n_strips, n_segs;
-  pplbm::fused_shape(c->nx, c->ny, kMinSegLen, &n_strips, &n_segs);
+  pplbm::fused_shape(c->nx, c->ny, kMinSegLen, false, &n_strips, &n_segs);  // the larger count
   size_t fused = (size_t)n_strips * n_segs;
   size_t two = (size_t)pplbm::two_pass_blocks(c->nx, c->ny);
   return std::max(fused, two);

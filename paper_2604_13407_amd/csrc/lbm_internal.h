@@ -22,7 +22,11 @@ struct StepLaunch {
 };
 
 int two_pass_blocks(int nx, int ny);
-void fused_shape(int nx, int ny, int seg_len, int* n_strips, int* n_segs);
+// Whether the step runs the aligned 64-column strip kernel (fast path on a
+// width that is a multiple of 64), and the strip/segment counts of the fused
+// kernels (one reduction record per strip and segment).
+bool aligned_strips(int nx, int fast);
+void fused_shape(int nx, int ny, int seg_len, bool aligned, int* n_strips, int* n_segs);
 
 template <class S>
 hipError_t launch_init(const StepParams& p, const double* rho0, const double* ux0, const double* uy0, void* fa,

@@ -366,6 +366,26 @@ __device__ inline double wave_shl1(double v) {
   return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
+// Lane l receives lane l-1's value and lane 0 receives `fill`: DPP wave_shr:1
+// whose destination starts as `fill` (a lane without a source lane keeps it).
+// One instruction per half and no lane select: a select around a DPP move
+// can be turned into a branch that masks the source lane off.
+__device__ inline double wave_shr1_fill(double v, double fill) {
+  unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  unsigned long long f = __builtin_bit_cast(unsigned long long, fill);
+  int lo = __builtin_amdgcn_update_dpp((int)(unsigned)f, (int)(unsigned)b, 0x138, 0xf, 0xf, false);
+  int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(f >> 32), (int)(unsigned)(b >> 32), 0x138, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+// Lane l receives lane l+1's value and lane 63 receives `fill`: DPP wave_shl:1.
+__device__ inline double wave_shl1_fill(double v, double fill) {
+  unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  unsigned long long f = __builtin_bit_cast(unsigned long long, fill);
+  int lo = __builtin_amdgcn_update_dpp((int)(unsigned)f, (int)(unsigned)b, 0x130, 0xf, 0xf, false);
+  int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(f >> 32), (int)(unsigned)(b >> 32), 0x130, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
 // Row geometry, uniform across the wavefront.
 struct RowGeo {
   bool real;         // the row is a lattice row (in the box, or wrapped periodically)
@@ -473,14 +493,22 @@ __device__ inline void pull_offsets_interior(const March& m, const RowGeo& g, un
   }
 }
 
+// Issues the 9 pulled loads of row y.  A row that will not be used (`live`
+// false: beyond the end of the run) is still issued, with every offset out
+// of the buffer's range, so its loads return 0 without touching memory.  The
+// loads are then unconditional, and the wait before each row's first use can
+// count exactly the loads and stores issued after it (a conditional issue
+// makes the wait drain the whole queue, including the rows in flight).
 template <class S, bool INTERIOR>
-__device__ inline void issue_row(const StepParams& p, const March& m, int y, S raw[9], RowGeo& g) {
+__device__ inline void issue_row(const StepParams& p, const March& m, int y, bool live, S raw[9], RowGeo& g) {
   g = row_geo(p, y);
   unsigned off[9];
   if (INTERIOR)
     pull_offsets_interior<S>(m, g, off);
   else
     pull_offsets<S>(g, m.c, m.N, m.bytes, off);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) off[i] = live ? off[i] : m.bytes;
   load_row<S>(m.in, off, raw);
 }
 
@@ -491,7 +519,7 @@ template <class S, bool REDUCE, bool INTERIOR>
 __device__ inline void march_row(const StepParams& p, const March& m, int y, const S cur0[9], const S cur1[9],
                                  S nxt[9], const RowScal& tm, const RowScal& t0, RowScal& t1, RowScal& t2,
                                  double* acc) {
-  if (y + 2 <= m.y1) issue_row<S, INTERIOR>(p, m, y + 2, nxt, t2.g);
+  issue_row<S, INTERIOR>(p, m, y + 2, y + 2 <= m.y1, nxt, t2.g);
   row_state<S>(p, cur1, t1.g.real && m.c.real, t1);
   const double pW = wave_shr1(t0.psi), pE = wave_shl1(t0.psi);
   const double pSW = wave_shr1(tm.psi), pSE = wave_shl1(tm.psi);
@@ -535,7 +563,7 @@ template <class S, bool REDUCE, bool INTERIOR>
 __device__ inline void march_row4(const StepParams& p, const March& m, int y, const S cur0[9], const S cur1[9],
                                   S nxt[9], const RowScal& tm, const RowScal& t0, RowScal& t1, RowScal& t3,
                                   double* acc) {
-  if (y + 3 <= m.y1) issue_row<S, INTERIOR>(p, m, y + 3, nxt, t3.g);
+  issue_row<S, INTERIOR>(p, m, y + 3, y + 3 <= m.y1, nxt, t3.g);
   row_state<S>(p, cur1, t1.g.real && m.c.real, t1);
   const double pW = wave_shr1(t0.psi), pE = wave_shl1(t0.psi);
   const double pSW = wave_shr1(tm.psi), pSE = wave_shl1(tm.psi);
@@ -582,9 +610,9 @@ __device__ inline void march(const StepParams& p, const March& m, int y0, double
     S ra[9], rb[9], rc[9];
     RowScal ta, tb, tc;
     // row r lives in slot (r - y0 + 1) mod 3: y0-1 -> c, y0 -> a, y0+1 -> b
-    issue_row<S, INTERIOR>(p, m, y0 - 1, rc, tc.g);
-    issue_row<S, INTERIOR>(p, m, y0, ra, ta.g);
-    issue_row<S, INTERIOR>(p, m, y0 + 1, rb, tb.g);
+    issue_row<S, INTERIOR>(p, m, y0 - 1, true, rc, tc.g);
+    issue_row<S, INTERIOR>(p, m, y0, true, ra, ta.g);
+    issue_row<S, INTERIOR>(p, m, y0 + 1, true, rb, tb.g);
     row_state<S>(p, rc, tc.g.real && m.c.real, tc);
     row_state<S>(p, ra, ta.g.real && m.c.real, ta);
     for (int y = y0; y < m.y1; y += 3) {
@@ -598,10 +626,10 @@ __device__ inline void march(const StepParams& p, const March& m, int y0, double
     S r0[9], r1[9], r2[9], r3[9];
     RowScal t0, t1, t2, t3;
     // row r lives in slot (r - y0 + 1) mod 4: y0-1 -> 0, y0 -> 1, y0+1 -> 2, y0+2 -> 3
-    issue_row<S, INTERIOR>(p, m, y0 - 1, r0, t0.g);
-    issue_row<S, INTERIOR>(p, m, y0, r1, t1.g);
-    issue_row<S, INTERIOR>(p, m, y0 + 1, r2, t2.g);
-    if (y0 + 2 <= m.y1) issue_row<S, INTERIOR>(p, m, y0 + 2, r3, t3.g);
+    issue_row<S, INTERIOR>(p, m, y0 - 1, true, r0, t0.g);
+    issue_row<S, INTERIOR>(p, m, y0, true, r1, t1.g);
+    issue_row<S, INTERIOR>(p, m, y0 + 1, true, r2, t2.g);
+    issue_row<S, INTERIOR>(p, m, y0 + 2, y0 + 2 <= m.y1, r3, t3.g);
     row_state<S>(p, r0, t0.g.real && m.c.real, t0);
     row_state<S>(p, r1, t1.g.real && m.c.real, t1);
     for (int y = y0; y < m.y1; y += 4) {
@@ -693,6 +721,253 @@ __global__ __launch_bounds__(256) void fast_kernel(StepParams p, const S* __rest
   }
 }
 
+// ------------------------------------------------------------------ aligned strip kernel
+//
+// The fast kernel for lattices whose width is a multiple of 64.  A wavefront
+// owns 64 aligned columns x0 .. x0+63 (every lane a node), so each row of
+// each population is stored as whole aligned 256-byte (FP32) or 512-byte
+// (FP64) lines.  Overlapping 62-column strips store rows that straddle cache
+// lines shared with the neighbouring strip; measured on gfx950, the march
+// moves data markedly slower that way.  The pseudopotential of the columns
+// beside the strip (x0-1 for lane 0's stencil, x0+64 for lane 63's) comes from
+// a second row of 9 pulled loads in which only lanes 0 and 63 are in range:
+// lane 0 pulls column x0-1 and lane 63 column x0+64; the other lanes' offsets
+// are out of range, so those loads return 0 without a memory access.
+
+struct AMarch {
+  __amdgpu_buffer_rsrc_t in, out;
+  unsigned N, bytes;
+  ColGeo c;   // the lane's column
+  ColGeo h;   // lane 0: column x0-1, lane 63: column x0+64; real where that node exists
+  bool hl;    // lane 0 or lane 63
+  int y1;
+  unsigned colB[9], colH[9];  // byte offsets of the pulled columns (interior strips)
+};
+
+struct ARow {
+  double drho, jx, jy, psi;
+  double psih;  // psi of the halo column (lanes 0 and 63)
+  bool bad;
+  RowGeo g;
+};
+
+template <class S, bool INTERIOR>
+__device__ inline void aissue_row(const StepParams& p, const AMarch& m, int y, bool live, S raw[9], S rawh[9],
+                                  RowGeo& g) {
+  g = row_geo(p, y);
+  unsigned off[9], offh[9];
+  if (INTERIOR) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const int eyi = ey(i);
+      const unsigned row = eyi == 1 ? g.bot : (eyi == -1 ? g.top : g.own);
+      const unsigned rb = ((unsigned)i * m.N + row) * (unsigned)sizeof(S);
+      off[i] = rb + m.colB[i];
+      offh[i] = m.hl ? rb + m.colH[i] : m.bytes;
+    }
+  } else {
+    pull_offsets<S>(g, m.c, m.N, m.bytes, off);
+    pull_offsets<S>(g, m.h, m.N, m.bytes, offh);
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    off[i] = live ? off[i] : m.bytes;
+    offh[i] = live ? offh[i] : m.bytes;
+  }
+  load_row<S>(m.in, off, raw);
+  load_row<S>(m.in, offh, rawh);
+}
+
+template <class S>
+__device__ inline void arow_state(const StepParams& p, const AMarch& m, const S raw[9], const S rawh[9], ARow& t) {
+  double d[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) d[i] = (double)raw[i];
+  node_sums(d, t.drho, t.jx, t.jy);
+  bool bad;
+  const double ps = psi_of(p, p.rho_ref + t.drho, bad);
+  t.psi = t.g.real ? ps : p.psi_solid;
+  t.bad = t.g.real && bad;
+  double h = 0.0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) h += (double)rawh[i];
+  bool badh;
+  const double psh = psi_of(p, p.rho_ref + h, badh);
+  t.psih = (t.g.real && m.h.real) ? psh : p.psi_solid;
+}
+
+// Collide and store row y (`cur0`, `t0`), with psi of rows y-1 (`tm`) and
+// y+1 (`t1`, finished here from `cur1`); the loads of row y + AHEAD go into
+// `nxt` first.
+template <class S, bool REDUCE, bool INTERIOR, int AHEAD>
+__device__ inline void amarch_row(const StepParams& p, const AMarch& m, int y, const S cur0[9], const S cur1[9],
+                                  const S cur1h[9], S nxt[9], S nxth[9], const ARow& tm, const ARow& t0, ARow& t1,
+                                  ARow& tn, double* acc) {
+  aissue_row<S, INTERIOR>(p, m, y + AHEAD, y + AHEAD <= m.y1, nxt, nxth, tn.g);
+  arow_state<S>(p, m, cur1, cur1h, t1);
+  // lane 0's west and lane 63's east neighbours are the halo columns, whose
+  // psi those two lanes hold in psih
+  const double pW = wave_shr1_fill(t0.psi, t0.psih);
+  const double pE = wave_shl1_fill(t0.psi, t0.psih);
+  const double pSW = wave_shr1_fill(tm.psi, tm.psih);
+  const double pSE = wave_shl1_fill(tm.psi, tm.psih);
+  const double pNW = wave_shr1_fill(t1.psi, t1.psih);
+  const double pNE = wave_shl1_fill(t1.psi, t1.psih);
+  double d[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) d[i] = (double)cur0[i];
+  double Sx, Sy;
+  stencil_sums(pE, t1.psi, pW, tm.psi, pNE, pNW, pSW, pSE, Sx, Sy);
+  NodeMacro mac = collide_node(p, d, t0.drho, t0.jx, t0.jy, t0.psi, Sx, Sy);
+  const bool store = t0.g.real;
+  const unsigned k = t0.g.own + m.c.own;
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+    BufIO<S>::store((S)d[i], m.out, store ? ((unsigned)i * m.N + k) * (unsigned)sizeof(S) : m.bytes);
+  if (REDUCE && store) {
+    if (!INTERIOR) {
+      double wx = 0.0, wy = 0.0;
+#pragma unroll
+      for (int i = 1; i < 9; ++i) {
+        const int exi = ex(i), eyi = ey(i);
+        const bool wall = (eyi == 1 && t0.g.wall_b) || (eyi == -1 && t0.g.wall_t) || (exi == 1 && m.c.wall_l) ||
+                          (exi == -1 && m.c.wall_r);
+        if (wall) {
+          double both = 2.0 * ((double)cur0[i] + wgt(i) * p.rho_ref);
+          wx -= exi * both;
+          wy -= eyi * both;
+        }
+      }
+      acc[RED_WALLX] += wx;
+      acc[RED_WALLY] += wy;
+    }
+    accumulate_node(p, acc, p.rho_ref + t0.drho, t0.jx, t0.jy, mac, t0.bad);
+  }
+}
+
+// The march over rows y0 .. y1-1.  Float storage keeps three row slots (row
+// y+2 in flight while row y collides), double storage four (rows y+2, y+3).
+template <class S, bool REDUCE, bool INTERIOR>
+__device__ inline void amarch(const StepParams& p, const AMarch& m, int y0, double* acc) {
+  if (sizeof(S) == 4) {
+    S ra[9], rb[9], rc[9], ha[9], hb[9], hc[9];
+    ARow ta, tb, tc;
+    // row r lives in slot (r - y0 + 1) mod 3: y0-1 -> c, y0 -> a, y0+1 -> b
+    aissue_row<S, INTERIOR>(p, m, y0 - 1, true, rc, hc, tc.g);
+    aissue_row<S, INTERIOR>(p, m, y0, true, ra, ha, ta.g);
+    aissue_row<S, INTERIOR>(p, m, y0 + 1, true, rb, hb, tb.g);
+    arow_state<S>(p, m, rc, hc, tc);
+    arow_state<S>(p, m, ra, ha, ta);
+    for (int y = y0; y < m.y1; y += 3) {
+      amarch_row<S, REDUCE, INTERIOR, 2>(p, m, y, ra, rb, hb, rc, hc, tc, ta, tb, tc, acc);
+      if (y + 1 >= m.y1) break;
+      amarch_row<S, REDUCE, INTERIOR, 2>(p, m, y + 1, rb, rc, hc, ra, ha, ta, tb, tc, ta, acc);
+      if (y + 2 >= m.y1) break;
+      amarch_row<S, REDUCE, INTERIOR, 2>(p, m, y + 2, rc, ra, ha, rb, hb, tb, tc, ta, tb, acc);
+    }
+  } else {
+    S r0[9], r1[9], r2[9], r3[9], h0[9], h1[9], h2[9], h3[9];
+    ARow t0, t1, t2, t3;
+    // row r lives in slot (r - y0 + 1) mod 4: y0-1 -> 0, y0 -> 1, y0+1 -> 2, y0+2 -> 3
+    aissue_row<S, INTERIOR>(p, m, y0 - 1, true, r0, h0, t0.g);
+    aissue_row<S, INTERIOR>(p, m, y0, true, r1, h1, t1.g);
+    aissue_row<S, INTERIOR>(p, m, y0 + 1, true, r2, h2, t2.g);
+    aissue_row<S, INTERIOR>(p, m, y0 + 2, y0 + 2 <= m.y1, r3, h3, t3.g);
+    arow_state<S>(p, m, r0, h0, t0);
+    arow_state<S>(p, m, r1, h1, t1);
+    for (int y = y0; y < m.y1; y += 4) {
+      amarch_row<S, REDUCE, INTERIOR, 3>(p, m, y, r1, r2, h2, r0, h0, t0, t1, t2, t0, acc);
+      if (y + 1 >= m.y1) break;
+      amarch_row<S, REDUCE, INTERIOR, 3>(p, m, y + 1, r2, r3, h3, r1, h1, t1, t2, t3, t1, acc);
+      if (y + 2 >= m.y1) break;
+      amarch_row<S, REDUCE, INTERIOR, 3>(p, m, y + 2, r3, r0, h0, r2, h2, t2, t3, t0, t2, acc);
+      if (y + 3 >= m.y1) break;
+      amarch_row<S, REDUCE, INTERIOR, 3>(p, m, y + 3, r0, r1, h1, r3, h3, t3, t0, t1, t3, acc);
+    }
+  }
+}
+
+// Column geometry of column x (possibly one outside the box).
+__device__ inline ColGeo col_geo(const StepParams& p, int x, bool want) {
+  ColGeo c;
+  const int nx = p.nx;
+  int xw = x;
+  c.real = want;
+  if (x < 0 || x >= nx) {
+    if (p.periodic_x)
+      xw = x < 0 ? x + nx : x - nx;
+    else
+      c.real = false, xw = 0;
+  }
+  if (!want) xw = 0;
+  int xl = xw - 1, xr = xw + 1;
+  c.wall_l = c.wall_r = false;
+  if (xl < 0) {
+    if (p.periodic_x) xl += nx;
+    else c.wall_l = true, xl = 0;
+  }
+  if (xr >= nx) {
+    if (p.periodic_x) xr -= nx;
+    else c.wall_r = true, xr = 0;
+  }
+  c.own = (unsigned)xw;
+  c.left = (unsigned)xl;
+  c.right = (unsigned)xr;
+  return c;
+}
+
+template <class S, bool REDUCE>
+__global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __restrict__ f, S* __restrict__ fo,
+                                                      int n_strips, int seg_len, int n_segs, int groups, int per_xcd,
+                                                      double* __restrict__ partials) {
+  const int b = blockIdx.x;
+  const int L = (b & 7) * per_xcd + (b >> 3);
+  const int seg = L / groups;
+  const int group = L - seg * groups;
+  const int wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int strip = group * 4 + wv;
+  if (seg >= n_segs || strip >= n_strips) return;  // uniform per wavefront
+
+  AMarch m;
+  m.N = (unsigned)p.nx * (unsigned)p.ny;
+  m.bytes = 9u * m.N * (unsigned)sizeof(S);
+  m.in = __builtin_amdgcn_make_buffer_rsrc((void*)f, (short)0, (int)m.bytes, 0x00020000);
+  m.out = __builtin_amdgcn_make_buffer_rsrc((void*)fo, (short)0, (int)m.bytes, 0x00020000);
+  const int x0 = strip * WAVE;
+  m.hl = lane == 0 || lane == WAVE - 1;
+  m.c = col_geo(p, x0 + lane, true);
+  m.h = col_geo(p, lane == 0 ? x0 - 1 : x0 + WAVE, m.hl);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int exi = ex(i);
+    m.colB[i] = (exi == 1 ? m.c.left : (exi == -1 ? m.c.right : m.c.own)) * (unsigned)sizeof(S);
+    m.colH[i] = (exi == 1 ? m.h.left : (exi == -1 ? m.h.right : m.h.own)) * (unsigned)sizeof(S);
+  }
+  const int y0 = seg * seg_len;
+  m.y1 = min(y0 + seg_len, p.ny);
+
+  double acc[RED_COUNT];
+#pragma unroll
+  for (int q = 0; q < RED_COUNT; ++q) acc[q] = 0.0;
+
+  // Interior strips (the pulls of columns x0-1 .. x0+64 stay inside the box
+  // without wrapping) of y-periodic lattices take the select-free offsets.
+  const bool interior = p.periodic_y && x0 >= 2 && x0 + WAVE + 1 <= p.nx - 1;
+  if (interior)
+    amarch<S, REDUCE, true>(p, m, y0, acc);
+  else
+    amarch<S, REDUCE, false>(p, m, y0, acc);
+
+  if (REDUCE) {
+#pragma unroll
+    for (int q = 0; q < RED_COUNT; ++q) {
+      double v = wave_sum(acc[q]);
+      if (lane == 0) partials[(size_t)(seg * n_strips + strip) * RED_COUNT + q] = v;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ finalize
 __global__ void finalize_kernel(const double* __restrict__ partials, int n_parts, double* __restrict__ out) {
   __shared__ double lds[RED_COUNT][256];
@@ -724,8 +999,10 @@ static dim3 node_grid(const StepParams& p, dim3 blk) {
 
 int two_pass_blocks(int nx, int ny) { return ((nx + 63) / 64) * ((ny + 3) / 4); }
 
-void fused_shape(int nx, int ny, int seg_len, int* n_strips, int* n_segs) {
-  *n_strips = (nx + STRIP - 1) / STRIP;
+bool aligned_strips(int nx, int fast) { return fast && nx % WAVE == 0; }
+
+void fused_shape(int nx, int ny, int seg_len, bool aligned, int* n_strips, int* n_segs) {
+  *n_strips = aligned ? nx / WAVE : (nx + STRIP - 1) / STRIP;
   *n_segs = (ny + seg_len - 1) / seg_len;
 }
 
@@ -751,9 +1028,21 @@ hipError_t launch_step(const StepParams& p, const StepLaunch& L, hipStream_t st)
     else
       hipLaunchKernelGGL((collide_kernel<S, false>), grd, blk, 0, st, p, f, fo, L.mask, L.wall_u,
                          (const double*)L.psi, L.partials);
+  } else if (aligned_strips(p.nx, L.fast)) {
+    int n_strips, n_segs;
+    fused_shape(p.nx, p.ny, L.seg_len, true, &n_strips, &n_segs);
+    int groups = (n_strips + 3) / 4;
+    int total = groups * n_segs;
+    int per_xcd = (total + 7) / 8;
+    if (L.reduce)
+      hipLaunchKernelGGL((aligned_kernel<S, true>), dim3(8 * per_xcd), dim3(256), 0, st, p, f, fo, n_strips,
+                         L.seg_len, n_segs, groups, per_xcd, L.partials);
+    else
+      hipLaunchKernelGGL((aligned_kernel<S, false>), dim3(8 * per_xcd), dim3(256), 0, st, p, f, fo, n_strips,
+                         L.seg_len, n_segs, groups, per_xcd, L.partials);
   } else if (L.fast) {
     int n_strips, n_segs;
-    fused_shape(p.nx, p.ny, L.seg_len, &n_strips, &n_segs);
+    fused_shape(p.nx, p.ny, L.seg_len, false, &n_strips, &n_segs);
     int groups = (n_strips + 3) / 4;
     int total = groups * n_segs;
     int per_xcd = (total + 7) / 8;
@@ -765,7 +1054,7 @@ hipError_t launch_step(const StepParams& p, const StepLaunch& L, hipStream_t st)
                          n_segs, groups, per_xcd, L.partials);
   } else {
     int n_strips, n_segs;
-    fused_shape(p.nx, p.ny, L.seg_len, &n_strips, &n_segs);
+    fused_shape(p.nx, p.ny, L.seg_len, false, &n_strips, &n_segs);
     int waves = n_strips * n_segs;
     int blocks = (waves + 3) / 4;
     if (L.reduce)

@@ -4,6 +4,8 @@ Bars: FP64 path within 1e-12 of the oracle (relative to each field's scale);
 FP32 deviation path within 1e-5 relative in density and 1e-4 of the peak
 velocity.  Fused and two-pass kernels must agree with each other bitwise.
 """
+from dataclasses import replace
+
 import numpy as np
 import pytest
 import torch
@@ -88,6 +90,24 @@ def droplet_small():
     return w.with_size(130, 200, init_args={"centre": (64.5, 99.5), "radius": 25.0}, fy=-1e-5)
 
 
+def droplet_aligned():
+    # width 256 = four 64-column strips: two at the walls, two interior
+    w = WL.droplet()
+    return w.with_size(256, 160, init_args={"centre": (127.5, 79.5), "radius": 30.0}, fy=-1e-5)
+
+
+def periodic_aligned():
+    # width 192, periodic in x and y: the strips' side columns wrap around
+    w = WL.small_droplet(nx=192, ny=64, radius=12.0, g=1e-5)
+    return replace(w, name="periodic_aligned", periodic_x=True)
+
+
+def channel_aligned():
+    # width 128, walls in y (no strip takes the interior offsets)
+    w = WL.poiseuille_aligned()
+    return w.with_size(128, 60, init_args={"y0": 15, "y1": 45})
+
+
 CASES = [
     (lambda: WL.poiseuille_aligned(), 300),
     (lambda: WL.poiseuille_aligned(scheme=WL.SCHEME_ORIGINAL), 300),
@@ -95,6 +115,9 @@ CASES = [
     (lambda: annulus_small(), 60),
     (lambda: droplet_small(), 60),
     (lambda: WL.small_droplet(nx=70, ny=45, radius=9.0, g=1e-5, scheme=WL.SCHEME_ORIGINAL), 80),
+    (droplet_aligned, 60),
+    (periodic_aligned, 60),
+    (channel_aligned, 200),
 ]
 
 
@@ -142,9 +165,10 @@ def test_fused_and_two_pass_agree(case, precision):
         assert err <= 1e-14, (w.name, err)
 
 
+@pytest.mark.parametrize("make", [droplet_small, droplet_aligned])
 @pytest.mark.parametrize("precision", [LT.FP64, LT.FP32_DEV])
-def test_reductions_match_oracle(precision):
-    w = droplet_small()
+def test_reductions_match_oracle(precision, make):
+    w = make()
     lat = LT.Lattice.from_workload(w, precision=precision)
     recs = lat.step(40, reduce_every=10)
     assert [r["step"] for r in recs] == [10, 20, 30, 40]
@@ -179,9 +203,10 @@ def test_mass_conservation_fp64_with_mask():
     assert np.max(np.abs(m - m[0])) <= 1e-13 * m[0]
 
 
+@pytest.mark.parametrize("make", [droplet_small, droplet_aligned])
 @pytest.mark.parametrize("precision", [LT.FP64, LT.FP32_DEV])
-def test_checkpoint_resume_is_bitwise(precision):
-    w = droplet_small()
+def test_checkpoint_resume_is_bitwise(precision, make):
+    w = make()
     a = LT.Lattice.from_workload(w, precision=precision)
     a.step(10)
     saved = a.get_state()
@@ -206,14 +231,18 @@ def test_runs_are_deterministic():
     assert outs[0][1] == outs[1][1]
 
 
-@pytest.mark.parametrize("nx,ny,px,py", [(1, 1, True, True), (2, 3, True, True), (63, 17, False, False),
-                                         (64, 5, True, False), (125, 9, False, True), (200, 1, True, True)])
-def test_edge_shapes_fp64(nx, ny, px, py):
+@pytest.mark.parametrize("nx,ny,px,py,use_mask", [
+    (1, 1, True, True, True), (2, 3, True, True, True), (63, 17, False, False, True), (64, 5, True, False, True),
+    (125, 9, False, True, True), (200, 1, True, True, True),
+    # without a mask these take the aligned 64-column kernel
+    (64, 5, True, False, False), (128, 1, True, True, False), (64, 2, False, True, False),
+    (192, 7, False, False, False)])
+def test_edge_shapes_fp64(nx, ny, px, py, use_mask):
     rng = np.random.default_rng(nx * 100 + ny)
     w = WL.small_droplet()
     w = w.with_size(nx, ny, periodic_x=px, periodic_y=py, init="none", perturb=0.05, seed=nx + ny)
     mask = None
-    if nx * ny > 50:
+    if use_mask and nx * ny > 50:
         mask = (rng.random((ny, nx)) < 0.1).astype(np.uint8)
     lat = LT.Lattice(nx, ny, px, py, LT.FP64, LT.KERNEL_FUSED, mask=mask)
     lat.set_eos(w.eos_kind, w.a, w.b, w.R, w.T, w.k_eos)
