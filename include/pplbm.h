@@ -171,7 +171,8 @@ int lbm_init_equilibrium(lbm_lattice* h, const double* rho0_dev, const double* u
 int lbm_step(lbm_lattice* h, int64_t n, int32_t reduce_every, lbm_reduction* out_host, int64_t n_out);
 
 /* Launch tuning of the fused kernels: rows each wavefront marches through
- * (16 <= rows <= 4096; 0 restores the default chosen from the lattice size).
+ * (4 <= rows <= 4096; 0 restores the default chosen from the lattice size and
+ * precision).
  * Results do not depend on it. */
 int lbm_set_rows_per_wave(lbm_lattice* h, int32_t rows);
 

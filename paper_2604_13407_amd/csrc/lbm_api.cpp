@@ -101,15 +101,26 @@ bool config_ok(const lbm_config* c, std::string& why) {
   return true;
 }
 
-constexpr int kMinSegLen = 16;
+constexpr int kMinSegLen = 4;
 
-// Rows each wavefront marches.  Short runs win on gfx950: a run starts with
-// three rows of loads in flight at once, and many short runs keep the load
-// queues fuller than a few long ones (measured on the 2048 x 16384 lattice:
-// 16 rows beats 64 by 15% and one-round runs of ~190 rows by 20%).
-int default_seg_len(int nx, int ny) {
-  (void)nx;
-  return std::min(kMinSegLen, std::max(ny, 1));
+// Rows each wavefront marches: the longest of 24, 16, 12, 8, 6 rows that
+// still gives the launch enough wavefronts to fill the chip (2,048 for float
+// storage, 1,024 for double, whose rows carry twice the bytes).  A run
+// recomputes the pseudopotential of the two rows beside it, so longer runs
+// read less; but a run keeps only a few rows of loads in flight, so the chip
+// needs many runs at once.  Measured on gfx950: 2048 x 16384, float: 24 rows
+// 64.4k MLUPS, 16 rows 63.7k, 64 rows ~15% slower; 512 x 2048, float: 8 rows
+// 48.5k, 16 rows 42.2k; double: 16 rows 35.2k, 8 rows 33.4k.
+int default_seg_len(const lbm_lattice* h) {
+  const int nx = h->cfg.nx, ny = std::max(h->cfg.ny, 1);
+  int n_strips, n_segs;
+  const bool aligned = pplbm::aligned_strips(nx, fast_path(h) ? 1 : 0);
+  const long target = h->cfg.precision == LBM_FP64 ? 1024 : 2048;
+  for (int rows : {24, 16, 12, 8, 6}) {
+    pplbm::fused_shape(nx, ny, rows, aligned, &n_strips, &n_segs);
+    if ((long)n_strips * n_segs >= target) return std::min(rows, ny);
+  }
+  return std::min(kMinSegLen, ny);
 }
 
 size_t max_parts_for(const lbm_config* c) {
@@ -272,7 +283,7 @@ int lbm_create(const lbm_config* cfg, const lbm_buffers* buf, void* hip_stream, 
   h->k2 = NAN;
   h->q2_policy = LBM_Q2_DEFAULT;
   h->rho_s = 0.0;
-  h->seg_len = default_seg_len(cfg->nx, cfg->ny);
+  h->seg_len = default_seg_len(h);
   Layout L = layout_for(cfg);
   char* ws = (char*)buf->workspace;
   h->partials = (double*)(ws + L.partials);
@@ -428,10 +439,10 @@ int lbm_step(lbm_lattice* h, int64_t n, int32_t reduce_every, lbm_reduction* out
 int lbm_set_rows_per_wave(lbm_lattice* h, int32_t rows) {
   if (!h) return LBM_ERR_INVALID_ARG;
   if (rows == 0) {
-    h->seg_len = default_seg_len(h->cfg.nx, h->cfg.ny);
+    h->seg_len = default_seg_len(h);
     return LBM_OK;
   }
-  if (rows < kMinSegLen || rows > 4096) return fail(h, LBM_ERR_INVALID_ARG, "rows per wave must be in [16, 4096]");
+  if (rows < kMinSegLen || rows > 4096) return fail(h, LBM_ERR_INVALID_ARG, "rows per wave must be in [4, 4096]");
   h->seg_len = rows;
   return LBM_OK;
 }

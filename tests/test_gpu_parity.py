@@ -268,3 +268,20 @@ def test_edge_shapes_fp64(nx, ny, px, py, use_mask):
         scale = field_scale(k, om[k][fl], psi_max) if fl.any() else 1.0
         err = np.max(np.abs(g[k][fl] - om[k][fl])) / scale if fl.any() else 0.0
         assert err <= 1e-12, (k, err)
+
+
+@pytest.mark.parametrize("make", [droplet_small, droplet_aligned])
+@pytest.mark.parametrize("precision", [LT.FP64, LT.FP32_DEV])
+def test_rows_per_wave_do_not_change_results(precision, make):
+    w = make()
+    states, recs = [], []
+    for rows in (0, 4, 7, 24, 100):
+        lat = LT.Lattice.from_workload(w, precision=precision)
+        lat.set_rows_per_wave(rows)
+        recs.append(lat.step(20, reduce_every=10))
+        torch.cuda.synchronize()
+        states.append(lat.state().clone())
+    for s, r in zip(states[1:], recs[1:]):
+        assert torch.equal(s, states[0])
+        for a, b in zip(r, recs[0]):
+            assert a["mass"] == pytest.approx(b["mass"], rel=1e-14)
