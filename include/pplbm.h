@@ -219,7 +219,8 @@ int lbm_set_state(lbm_lattice* h, const void* src_dev, int64_t step);
  * to the initial density field, the magnitude |F_ext| of the body force or
  * gravity (direction held fixed) and the interaction strength G.  They are
  * computed in double for both precisions; for LBM_FP32_DEV they are those of
- * the run as stored (the linearisation point is the FP32 trajectory).
+ * the run as stored (the linearisation point is the FP32 trajectory) and the
+ * per-step adjoint of the pulled populations is stored in float.
  * Memory: the forward pass saves fbar every checkpoint_every steps; the
  * backward pass replays each segment from its checkpoint, keeping
  * rho - rho_ref, j and psi of every step of the segment (32 bytes per node and
@@ -239,8 +240,9 @@ typedef struct lbm_adjoint_cfg {
 
 /* Bytes of the adjoint workspace for this lattice and run:
  * ceil(N/K) + 2 population arrays, min(K, N) * 4 * nx * ny doubles of
- * trajectory and 23 * nx * ny doubles of adjoint fields (one more for
- * LBM_LOSS_UERR), plus small reduction buffers.
+ * trajectory, 18 * nx * ny values of the storage type and 5 * nx * ny doubles
+ * of adjoint fields (one more double for LBM_LOSS_UERR), plus small reduction
+ * buffers.
  * Pure host computation. */
 int lbm_adjoint_workspace_bytes(const lbm_config* cfg, const lbm_adjoint_cfg* a, size_t* bytes);
 

@@ -58,11 +58,12 @@ __global__ void traj_kernel(StepParams p, const S* __restrict__ f, const uint8_t
   adj_traj_node<S>(p, f, mask, traj, x, y);
 }
 
+template <class L>
 __global__ void adj_local_kernel(StepParams p, AdjStepArgs a) {
   int x = blockIdx.x * blockDim.x + threadIdx.x;
   int y = blockIdx.y * blockDim.y + threadIdx.y;
   double part[2] = {0.0, 0.0};
-  if (x < p.nx && y < p.ny) adj_local_node(p, a, x, y, part);
+  if (x < p.nx && y < p.ny) adj_local_node<L>(p, a, x, y, part);
   block_add(part, 2, a.param_acc, blockIdx.y * gridDim.x + blockIdx.x, 2);
 }
 
@@ -73,11 +74,12 @@ __global__ void adj_psi_kernel(StepParams p, AdjStepArgs a) {
   adj_psi_node(p, a, x, y);
 }
 
+template <class L>
 __global__ void adj_rho0_kernel(StepParams p, AdjStepArgs a, double* __restrict__ grad_rho0) {
   int x = blockIdx.x * blockDim.x + threadIdx.x;
   int y = blockIdx.y * blockDim.y + threadIdx.y;
   if (x >= p.nx || y >= p.ny) return;
-  grad_rho0[(size_t)y * p.nx + x] = adj_rho0_node(p, a, x, y);
+  grad_rho0[(size_t)y * p.nx + x] = adj_rho0_node<L>(p, a, x, y);
 }
 
 // ------------------------------------------------------------------ velocity-error loss
@@ -148,14 +150,16 @@ hipError_t launch_traj(const StepParams& p, const void* f, const uint8_t* mask, 
   return hipGetLastError();
 }
 
+template <class L>
 hipError_t launch_adj_step(const StepParams& p, const AdjStepArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(adj_local_kernel, agrid(p), dim3(64, 4), 0, st, p, a);
+  hipLaunchKernelGGL(adj_local_kernel<L>, agrid(p), dim3(64, 4), 0, st, p, a);
   hipLaunchKernelGGL(adj_psi_kernel, agrid(p), dim3(64, 4), 0, st, p, a);
   return hipGetLastError();
 }
 
+template <class L>
 hipError_t launch_adj_rho0(const StepParams& p, const AdjStepArgs& a, double* grad_rho0, hipStream_t st) {
-  hipLaunchKernelGGL(adj_rho0_kernel, agrid(p), dim3(64, 4), 0, st, p, a, grad_rho0);
+  hipLaunchKernelGGL(adj_rho0_kernel<L>, agrid(p), dim3(64, 4), 0, st, p, a, grad_rho0);
   return hipGetLastError();
 }
 
@@ -179,6 +183,10 @@ hipError_t launch_zero(double* ptr, size_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
+template hipError_t launch_adj_step<float>(const StepParams&, const AdjStepArgs&, hipStream_t);
+template hipError_t launch_adj_step<double>(const StepParams&, const AdjStepArgs&, hipStream_t);
+template hipError_t launch_adj_rho0<float>(const StepParams&, const AdjStepArgs&, double*, hipStream_t);
+template hipError_t launch_adj_rho0<double>(const StepParams&, const AdjStepArgs&, double*, hipStream_t);
 template hipError_t launch_traj<float>(const StepParams&, const void*, const uint8_t*, double*, hipStream_t);
 template hipError_t launch_traj<double>(const StepParams&, const void*, const uint8_t*, double*, hipStream_t);
 

@@ -84,10 +84,12 @@ AdjLayout adj_layout(const lbm_config* c, const lbm_adjoint_cfg* a) {
   off += L.state_bytes;
   L.traj = off;
   off = align256(off + (size_t)L.seg * 4 * nd);
+  // D: float for float storage, double for double storage
+  const size_t nl = L.n * elem_size(c);
   L.D0 = off;
-  off = align256(off + 9 * nd);
+  off = align256(off + 9 * nl);
   L.D1 = off;
-  off = align256(off + 9 * nd);
+  off = align256(off + 9 * nl);
   L.R0 = off;
   off = align256(off + nd);
   L.R1 = off;
@@ -229,7 +231,7 @@ int lbm_adjoint_backward(lbm_lattice* h, double* grad_rho0, double* grad_force, 
   const size_t n = L.n;
   const size_t sbytes = 9 * n * elem_size(&h->cfg);
   const int blocks = pplbm::adj_blocks(h->cfg.nx, h->cfg.ny);
-  double* D[2] = {at<double>(ws, L.D0), at<double>(ws, L.D1)};
+  void* D[2] = {ws + L.D0, ws + L.D1};
   double* R[2] = {at<double>(ws, L.R0), at<double>(ws, L.R1)};
   double* acc = at<double>(ws, L.acc);
   double* traj = at<double>(ws, L.traj);
@@ -279,7 +281,8 @@ int lbm_adjoint_backward(lbm_lattice* h, double* grad_rho0, double* grad_force, 
       } else if (t == N) {
         s.cU = h->adj.inv_den;
       }
-      e = pplbm::launch_adj_step(h->prm, s, h->stream);
+      e = fp64 ? pplbm::launch_adj_step<double>(h->prm, s, h->stream)
+               : pplbm::launch_adj_step<float>(h->prm, s, h->stream);
       if (e != hipSuccess) return hip_fail(h, e, "adjoint step launch");
       cur = 1 - cur;
     }
@@ -288,7 +291,8 @@ int lbm_adjoint_backward(lbm_lattice* h, double* grad_rho0, double* grad_force, 
     s.D_next = D[1 - cur];
     s.R_next = R[1 - cur];
     s.have_next = 1;
-    e = pplbm::launch_adj_rho0(h->prm, s, grad_rho0, h->stream);
+    e = fp64 ? pplbm::launch_adj_rho0<double>(h->prm, s, grad_rho0, h->stream)
+             : pplbm::launch_adj_rho0<float>(h->prm, s, grad_rho0, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "initial-state gradient launch");
   }
   double* pair = at<double>(ws, L.pair);

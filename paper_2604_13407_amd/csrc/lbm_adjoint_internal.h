@@ -8,13 +8,14 @@
 
 namespace pplbm {
 
-// One reverse step n.  Arrays are [plane][ny][nx] doubles.
+// One reverse step n.  Arrays are [plane][ny][nx]; D holds elements of type
+// L (float for float storage, double for double storage), the rest doubles.
 struct AdjStepArgs {
   const uint8_t* mask;      // solid nodes, or NULL
   const double* traj;       // [4]: rho - rho_ref, j_x, j_y, psi of step n's pulled state
-  const double* D_next;     // [9]: dL/d(pulled populations) of step n + 1 through its collision
+  const void* D_next;       // [9] L: dL/d(pulled populations) of step n + 1 through its collision
   const double* R_next;     // [1]: psi'(rho) dL/dpsi of step n + 1
-  double* D;                // [9]: output for step n
+  void* D;                  // [9] L: output for step n
   double* T;                // [3]: dL/dpsi_c, dL/dS_x, dL/dS_y of step n (scratch)
   double* R;                // [1]: output for step n
   double* param_acc;        // [blocks][2]: running dL/dG, dL/d|F_ext| per block
@@ -28,7 +29,9 @@ int adj_blocks(int nx, int ny);
 
 template <class S>
 hipError_t launch_traj(const StepParams& p, const void* f, const uint8_t* mask, double* traj, hipStream_t st);
+template <class L>
 hipError_t launch_adj_step(const StepParams& p, const AdjStepArgs& a, hipStream_t st);
+template <class L>
 hipError_t launch_adj_rho0(const StepParams& p, const AdjStepArgs& a, double* grad_rho0, hipStream_t st);
 // sum over fluid nodes of (ux - ut)^2 and ut^2 into out[0..1] (partials: adj_blocks * 2 doubles)
 hipError_t launch_uerr(const StepParams& p, const uint8_t* mask, const double* ux, const double* ut,

@@ -205,16 +205,18 @@ __host__ __device__ inline bool fluid_at(const StepParams& p, const uint8_t* __r
 // transpose of that step's pull.  P = D_next + R_next is the adjoint of the
 // pulled populations; fbar_i(x) went to x + e_i when that node is fluid, and
 // was bounced back into direction opp(i) at x otherwise.
+template <class L>
 __host__ __device__ inline double lambda_of(const StepParams& p, const AdjStepArgs& a, int x, int y, size_t k,
                                             int i) {
   const size_t N = (size_t)p.nx * p.ny;
-  if (i == 0) return a.D_next[k] + a.R_next[k];
+  const L* Dn = static_cast<const L*>(a.D_next);
+  if (i == 0) return (double)Dn[k] + a.R_next[k];
   int xn, yn;
   if (fluid_at(p, a.mask, x + ex(i), y + ey(i), xn, yn)) {
     const size_t kn = (size_t)yn * p.nx + xn;
-    return a.D_next[(size_t)i * N + kn] + a.R_next[kn];
+    return (double)Dn[(size_t)i * N + kn] + a.R_next[kn];
   }
-  return a.D_next[(size_t)opp(i) * N + k] + a.R_next[k];
+  return (double)Dn[(size_t)opp(i) * N + k] + a.R_next[k];
 }
 
 // Replay: rho - rho_ref, j and psi of the state f pulled to node (x, y)
@@ -251,7 +253,9 @@ __host__ __device__ inline double psi_traj(const StepParams& p, const double* __
 
 // Reverse of node (x, y)'s step n: gathers lambda^n from step n + 1, adds
 // the loss's direct sensitivities at step n, reverses the collision.  Writes
-// D^n and T^n of the node; adds its dL/dG, dL/d|F_ext| shares to part[0..1].
+// D^n (rounded to L) and T^n of the node; adds its dL/dG, dL/d|F_ext| shares
+// to part[0..1].
+template <class L>
 __host__ __device__ inline void adj_local_node(const StepParams& p, const AdjStepArgs& a, int x, int y,
                                                double part[2]) {
   const size_t N = (size_t)p.nx * p.ny;
@@ -261,7 +265,7 @@ __host__ __device__ inline void adj_local_node(const StepParams& p, const AdjSte
     // lambda^n(x): transpose of step n+1's pull (zero after the last step)
     double ob[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) ob[i] = a.have_next ? lambda_of(p, a, x, y, k, i) : 0.0;
+    for (int i = 0; i < 9; ++i) ob[i] = a.have_next ? lambda_of<L>(p, a, x, y, k, i) : 0.0;
     const double drho = a.traj[k], jx = a.traj[N + k], jy = a.traj[2 * N + k];
     const double* psi = a.traj + 3 * N;
     const double pc = psi[k];
@@ -294,7 +298,7 @@ __host__ __device__ inline void adj_local_node(const StepParams& p, const AdjSte
     AdjOut o;
     collide_node_adjoint(p, drho, jx, jy, pc, Sx, Sy, ob, ls, o);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) a.D[(size_t)i * N + k] = o.dd[i];
+    for (int i = 0; i < 9; ++i) static_cast<L*>(a.D)[(size_t)i * N + k] = (L)o.dd[i];
     a.T[k] = o.psi_c;
     a.T[N + k] = o.Sx;
     a.T[2 * N + k] = o.Sy;
@@ -302,7 +306,7 @@ __host__ __device__ inline void adj_local_node(const StepParams& p, const AdjSte
     part[1] += o.g;
   } else {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) a.D[(size_t)i * N + k] = 0.0;
+    for (int i = 0; i < 9; ++i) static_cast<L*>(a.D)[(size_t)i * N + k] = (L)0;
     a.T[k] = 0.0;
     a.T[N + k] = 0.0;
     a.T[2 * N + k] = 0.0;
@@ -335,12 +339,13 @@ __host__ __device__ inline void adj_psi_node(const StepParams& p, const AdjStepA
 
 // dL/drho0(x) = sum_i w_i lambda^0_i(x), since fbar^0_i = w_i rho0 at rest
 // (a.D_next, a.R_next: step 1).
+template <class L>
 __host__ __device__ inline double adj_rho0_node(const StepParams& p, const AdjStepArgs& a, int x, int y) {
   const size_t k = (size_t)y * p.nx + x;
   if (a.mask && a.mask[k]) return 0.0;
   double g = 0.0;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) g += wgt(i) * lambda_of(p, a, x, y, k, i);
+  for (int i = 0; i < 9; ++i) g += wgt(i) * lambda_of<L>(p, a, x, y, k, i);
   return g;
 }
 

@@ -119,8 +119,8 @@ def test_adjoint_workspace_size_and_validation():
     n = 64 * 32
     assert L.lbm_adjoint_workspace_bytes(C.byref(c), C.byref(acfg()), C.byref(b)) == 0
     # 4 checkpoints (steps 0, 30, 60, 90) + 2 replay arrays of FP32 populations, 30 trajectory
-    # slots of 4 doubles, 23 doubles of adjoint fields per node
-    assert b.value >= (4 + 2) * 9 * n * 4 + 30 * 4 * n * 8 + 23 * n * 8
+    # slots of 4 doubles, adjoint fields of 18 floats and 5 doubles per node
+    assert b.value >= (4 + 2) * 9 * n * 4 + 30 * 4 * n * 8 + (18 * 4 + 5 * 8) * n
     assert b.value % 256 == 0
     small = b.value
     assert L.lbm_adjoint_workspace_bytes(C.byref(c), C.byref(acfg(checkpoint_every=10)), C.byref(b)) == 0
