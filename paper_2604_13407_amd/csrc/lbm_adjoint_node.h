@@ -193,12 +193,44 @@ __host__ __device__ inline void collide_node_adjoint(const StepParams& p, double
 }
 
 // ---------------------------------------------------------------- lattice-level reverse step
-// Whether (x, y) is a fluid node of the box (wrapped index in xw, yw).
-__host__ __device__ inline bool fluid_at(const StepParams& p, const uint8_t* __restrict__ mask, int x, int y,
-                                         int& xw, int& yw) {
-  bool inside;
-  bool sol = solid_at(p, mask, x, y, xw, yw, inside);
-  return !sol;
+// The eight neighbours x + e_i of a node (i = 1..8): index (wrapped across
+// periodic axes), whether the position is inside the box, whether it is a
+// fluid node.  Computed once per node from the wrapped columns x-1, x, x+1 and
+// rows y-1, y, y+1.
+struct Nbrs {
+  size_t k[9];
+  bool inside[9];
+  bool fluid[9];
+};
+
+__host__ __device__ inline void neighbours(const StepParams& p, const uint8_t* __restrict__ mask, int x, int y,
+                                           Nbrs& nb) {
+  int xs[3], ys[3];
+  bool xin[3], yin[3];
+#pragma unroll
+  for (int d = -1; d <= 1; ++d) {
+    int xx = x + d, yy = y + d;
+    bool xi = true, yi = true;
+    if (xx < 0 || xx >= p.nx) {
+      xi = p.periodic_x != 0;
+      xx = xx < 0 ? xx + p.nx : xx - p.nx;
+    }
+    if (yy < 0 || yy >= p.ny) {
+      yi = p.periodic_y != 0;
+      yy = yy < 0 ? yy + p.ny : yy - p.ny;
+    }
+    xs[d + 1] = xi ? xx : 0;
+    ys[d + 1] = yi ? yy : 0;
+    xin[d + 1] = xi;
+    yin[d + 1] = yi;
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int cx = ex(i) + 1, cy = ey(i) + 1;
+    nb.inside[i] = xin[cx] && yin[cy];
+    nb.k[i] = (size_t)ys[cy] * p.nx + xs[cx];
+    nb.fluid[i] = nb.inside[i] && !(mask && mask[nb.k[i]]);
+  }
 }
 
 // lambda_i(x) = dL/dfbar_i(x) of the state step n + 1 pulls from: the
@@ -206,16 +238,11 @@ __host__ __device__ inline bool fluid_at(const StepParams& p, const uint8_t* __r
 // pulled populations; fbar_i(x) went to x + e_i when that node is fluid, and
 // was bounced back into direction opp(i) at x otherwise.
 template <class L>
-__host__ __device__ inline double lambda_of(const StepParams& p, const AdjStepArgs& a, int x, int y, size_t k,
-                                            int i) {
+__host__ __device__ inline double lambda_of(const StepParams& p, const AdjStepArgs& a, const Nbrs& nb, int i) {
   const size_t N = (size_t)p.nx * p.ny;
   const L* Dn = static_cast<const L*>(a.D_next);
-  if (i == 0) return (double)Dn[k] + a.R_next[k];
-  int xn, yn;
-  if (fluid_at(p, a.mask, x + ex(i), y + ey(i), xn, yn)) {
-    const size_t kn = (size_t)yn * p.nx + xn;
-    return (double)Dn[(size_t)i * N + kn] + a.R_next[kn];
-  }
+  const size_t k = nb.k[0];
+  if (i != 0 && nb.fluid[i]) return (double)Dn[(size_t)i * N + nb.k[i]] + a.R_next[nb.k[i]];
   return (double)Dn[(size_t)opp(i) * N + k] + a.R_next[k];
 }
 
@@ -241,14 +268,10 @@ __host__ __device__ inline void adj_traj_node(const StepParams& p, const S* __re
   traj[3 * N + k] = ps;
 }
 
-// psi of the replayed step at (x, y), psi_s outside the box.
-__host__ __device__ inline double psi_traj(const StepParams& p, const double* __restrict__ psi, const uint8_t* mask,
-                                           int x, int y) {
-  int xw, yw;
-  bool inside;
-  solid_at(p, mask, x, y, xw, yw, inside);
-  if (!inside) return p.psi_solid;
-  return psi[(size_t)yw * p.nx + xw];
+// psi of the replayed step at neighbour i, psi_s outside the box (solid
+// nodes inside the box carry psi_s in the trajectory).
+__host__ __device__ inline double psi_nbr(const StepParams& p, const double* __restrict__ psi, const Nbrs& nb, int i) {
+  return nb.inside[i] ? psi[nb.k[i]] : p.psi_solid;
 }
 
 // Reverse of node (x, y)'s step n: gathers lambda^n from step n + 1, adds
@@ -262,18 +285,19 @@ __host__ __device__ inline void adj_local_node(const StepParams& p, const AdjSte
   const size_t k = (size_t)y * p.nx + x;
   const bool fluid = !(a.mask && a.mask[k]);
   if (fluid) {
+    Nbrs nb;
+    neighbours(p, a.mask, x, y, nb);
     // lambda^n(x): transpose of step n+1's pull (zero after the last step)
     double ob[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) ob[i] = a.have_next ? lambda_of<L>(p, a, x, y, k, i) : 0.0;
+    for (int i = 0; i < 9; ++i) ob[i] = a.have_next ? lambda_of<L>(p, a, nb, i) : 0.0;
     const double drho = a.traj[k], jx = a.traj[N + k], jy = a.traj[2 * N + k];
     const double* psi = a.traj + 3 * N;
     const double pc = psi[k];
     double Sx, Sy;
-    stencil_sums(psi_traj(p, psi, a.mask, x + 1, y), psi_traj(p, psi, a.mask, x, y + 1),
-                 psi_traj(p, psi, a.mask, x - 1, y), psi_traj(p, psi, a.mask, x, y - 1),
-                 psi_traj(p, psi, a.mask, x + 1, y + 1), psi_traj(p, psi, a.mask, x - 1, y + 1),
-                 psi_traj(p, psi, a.mask, x - 1, y - 1), psi_traj(p, psi, a.mask, x + 1, y - 1), Sx, Sy);
+    stencil_sums(psi_nbr(p, psi, nb, 1), psi_nbr(p, psi, nb, 2), psi_nbr(p, psi, nb, 3), psi_nbr(p, psi, nb, 4),
+                 psi_nbr(p, psi, nb, 5), psi_nbr(p, psi, nb, 6), psi_nbr(p, psi, nb, 7), psi_nbr(p, psi, nb, 8), Sx,
+                 Sy);
     // the loss's direct sensitivities at this step
     LossSens ls = {0, 0, 0, 0, 0, 0, 0, 0};
     const double r = p.rho_ref + drho;
@@ -321,14 +345,16 @@ __host__ __device__ inline void adj_psi_node(const StepParams& p, const AdjStepA
     a.R[k] = 0.0;
     return;
   }
-  // psi(x) enters S(x - e_k) with weight w_k e_k
+  // psi(x) enters S(x - e_i) = S(x + e_opp(i)) with weight w_i e_i
+  Nbrs nb;
+  neighbours(p, a.mask, x, y, nb);
   double pb = a.T[k];
   const double w1 = 1.0 / 3.0, w2 = 1.0 / 12.0;
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
-    int xs, ys;
-    if (fluid_at(p, a.mask, x - ex(i), y - ey(i), xs, ys)) {
-      const size_t ks = (size_t)ys * p.nx + xs;
+    const int o = opp(i);
+    if (nb.fluid[o]) {
+      const size_t ks = nb.k[o];
       const double w = i <= 4 ? w1 : w2;
       pb += w * (ex(i) * a.T[N + ks] + ey(i) * a.T[2 * N + ks]);
     }
@@ -343,9 +369,11 @@ template <class L>
 __host__ __device__ inline double adj_rho0_node(const StepParams& p, const AdjStepArgs& a, int x, int y) {
   const size_t k = (size_t)y * p.nx + x;
   if (a.mask && a.mask[k]) return 0.0;
+  Nbrs nb;
+  neighbours(p, a.mask, x, y, nb);
   double g = 0.0;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) g += wgt(i) * lambda_of<L>(p, a, x, y, k, i);
+  for (int i = 0; i < 9; ++i) g += wgt(i) * lambda_of<L>(p, a, nb, i);
   return g;
 }
 
