@@ -24,7 +24,7 @@ import time
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 ROOT = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "fast_kernel_fp32_droplet_2048x16384.json")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "aligned_kernel_fp32_droplet_2048x16384.json")
 
 
 def measured_traffic():
