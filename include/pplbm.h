@@ -17,9 +17,15 @@
  *  - The stored state is the post-collision field.  A step streams then
  *    collides.  "Macroscopic fields of the current state" are the pre-collision
  *    fields the next step would use.
- *  - Precision LBM_FP64 stores f in double.  LBM_FP32_DEV stores the
- *    deviations f_i - w_i * rho_ref in float.  Both compute the step in double
- *    (each population is rounded once when stored) and reduce in double.
+ *  - Precision LBM_FP64 stores f in double.  LBM_FP32_DEV stores, in float,
+ *    each population relative to its node's reference density:
+ *    s_i(x) = f_i(x) - w_i * rhat(x), with rhat(x) = rho_ref + c(x) and the
+ *    offset c kept as a tenth float plane of the population array (set from
+ *    the initial density; see lbm_rereference).  Deviations from a node's own
+ *    density are small in liquid and vapour alike, so the rounding of the
+ *    stored values stays small where a uniform reference would not.  Both
+ *    precisions compute the step in double (each population is rounded once
+ *    when stored) and reduce in double.
  *  - Ownership: the caller allocates and frees every device buffer (the
  *    population arrays, the workspace, the mask, the wall velocities and all
  *    outputs).  The library never allocates or frees device memory; it keeps
@@ -68,14 +74,16 @@ typedef struct lbm_config {
   int32_t periodic_y;      /* same for y */
   int32_t precision;       /* enum lbm_precision */
   int32_t kernel;          /* enum lbm_kernel: fused single kernel per step or two passes */
-  double rho_ref;          /* LBM_FP32_DEV: reference density of the stored deviations */
+  double rho_ref;          /* LBM_FP32_DEV: base of the per-node reference densities (any value
+                              near the densities; the offsets are stored relative to it) */
   int32_t log_capacity;    /* reduction records lbm_step may collect in one call (>= 1) */
   int32_t reserved;
 } lbm_config;
 
 /* Caller-owned device buffers. */
 typedef struct lbm_buffers {
-  void* f_a;               /* [9][ny][nx] populations (double or float per precision) */
+  void* f_a;               /* population array of lbm_state_bytes: [9][ny][nx] double, or
+                              [10][ny][nx] float (9 planes + the reference plane) */
   void* f_b;               /* second population array of the same size (ping-pong) */
   void* workspace;         /* lbm_workspace_bytes() bytes, 256-byte aligned */
   const uint8_t* mask;     /* [ny][nx], 1 = solid node, 0 = fluid; NULL = no solid nodes inside */
@@ -103,7 +111,8 @@ typedef struct lbm_lattice lbm_lattice;
 /* ABI version of the loaded library (LBM_ABI_VERSION). */
 int lbm_abi_version(void);
 
-/* Bytes of one population array (f_a or f_b) for this configuration. */
+/* Bytes of one population array (f_a or f_b) for this configuration: 9 planes
+ * of double, or 10 planes of float (the populations and the reference plane). */
 int lbm_state_bytes(const lbm_config* cfg, size_t* bytes);
 
 /* Bytes of the workspace (reduction partials, reduction log, two-pass
@@ -194,11 +203,19 @@ int lbm_reduce(lbm_lattice* h, lbm_reduction* out_host);
 /* Device pointer of the population array that holds the current state. */
 int lbm_state_ptr(const lbm_lattice* h, void** f_dev);
 
-/* Checkpoint / resume: copy the current populations to / from a caller
- * buffer of lbm_state_bytes (device, enqueued device-to-device copy).
- * lbm_set_state also sets the step counter. */
+/* Checkpoint / resume: copy the current state (populations, and for
+ * LBM_FP32_DEV the reference plane) to / from a caller buffer of
+ * lbm_state_bytes (device, enqueued device-to-device copy).  lbm_set_state
+ * also sets the step counter. */
 int lbm_get_state(lbm_lattice* h, void* dst_dev);
 int lbm_set_state(lbm_lattice* h, const void* src_dev, int64_t step);
+
+/* LBM_FP32_DEV: make every node's reference density its current density (the
+ * sum of its post-collision populations) and re-express the stored
+ * populations against it (one more rounding each); for long runs in which
+ * the density moves far from where it started.  No-op for LBM_FP64.  Enqueues
+ * one kernel; invalidates a recorded adjoint forward pass. */
+int lbm_rereference(lbm_lattice* h);
 
 /* ---------------------------------------------------------------------------
  * Discrete adjoint (reverse-mode gradients of a loss of a run).

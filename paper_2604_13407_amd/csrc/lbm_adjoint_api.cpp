@@ -72,7 +72,7 @@ AdjLayout adj_layout(const lbm_config* c, const lbm_adjoint_cfg* a) {
   L.n_ckpt = (N + K - 1) / K;
   L.seg = std::min<int64_t>(K, N);
   L.n_log = (a->loss == LBM_LOSS_DRAG) ? a->window : 1;
-  L.state_bytes = align256(9 * L.n * elem_size(c));
+  L.state_bytes = align256(state_bytes_of(c));
   const size_t nd = L.n * sizeof(double);
   const size_t blocks = (size_t)pplbm::adj_blocks(c->nx, c->ny);
   size_t off = 0;
@@ -150,7 +150,7 @@ int lbm_adjoint_forward(lbm_lattice* h, const lbm_adjoint_cfg* a, const double* 
   h->cur = 0;
   h->steps = 0;
   h->initialized = true;
-  const size_t sbytes = 9 * L.n * elem_size(&h->cfg);
+  const size_t sbytes = state_bytes_of(&h->cfg);
   double* log = at<double>(ws, L.log);
   for (int64_t t = 1; t <= N; ++t) {
     if ((t - 1) % K == 0) {
@@ -229,7 +229,7 @@ int lbm_adjoint_backward(lbm_lattice* h, double* grad_rho0, double* grad_force, 
   const bool fp64 = h->cfg.precision == LBM_FP64;
   const int64_t N = a.n_steps, K = a.checkpoint_every;
   const size_t n = L.n;
-  const size_t sbytes = 9 * n * elem_size(&h->cfg);
+  const size_t sbytes = state_bytes_of(&h->cfg);
   const int blocks = pplbm::adj_blocks(h->cfg.nx, h->cfg.ny);
   void* D[2] = {ws + L.D0, ws + L.D1};
   double* R[2] = {at<double>(ws, L.R0), at<double>(ws, L.R1)};

@@ -25,6 +25,12 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 size_t elem_size(const lbm_config* c) { return c->precision == LBM_FP64 ? sizeof(double) : sizeof(float); }
 
+// 9 population planes, plus the reference plane for float storage.
+size_t state_bytes_of(const lbm_config* c) {
+  const size_t planes = c->precision == LBM_FP64 ? 9 : 10;
+  return planes * (size_t)c->nx * (size_t)c->ny * elem_size(c);
+}
+
 int fail(lbm_lattice* h, int code, const std::string& msg) {
   if (h) h->err = msg;
   return code;
@@ -37,6 +43,7 @@ int hip_fail(lbm_lattice* h, hipError_t e, const char* what) {
 // The specialised strip kernel handles lattices without a mask or moving walls
 // whose population arrays fit 32-bit byte offsets.
 bool fast_path(const lbm_lattice* h) {
+  // 32-bit byte offsets into the 9 population planes
   double bytes = 9.0 * (double)h->cfg.nx * (double)h->cfg.ny * (double)elem_size(&h->cfg);
   return h->cfg.kernel == LBM_KERNEL_FUSED && !h->buf.mask && !h->buf.wall_u && bytes < 4294967040.0;
 }
@@ -221,7 +228,7 @@ int lbm_abi_version(void) { return LBM_ABI_VERSION; }
 int lbm_state_bytes(const lbm_config* cfg, size_t* bytes) {
   std::string why;
   if (!bytes || !config_ok(cfg, why)) return LBM_ERR_INVALID_ARG;
-  *bytes = (size_t)9 * cfg->nx * cfg->ny * elem_size(cfg);
+  *bytes = state_bytes_of(cfg);
   return LBM_OK;
 }
 
@@ -487,6 +494,16 @@ int lbm_reduce(lbm_lattice* h, lbm_reduction* out) {
   return fault_status(h, *out);
 }
 
+int lbm_rereference(lbm_lattice* h) {
+  if (!h) return LBM_ERR_INVALID_ARG;
+  if (!h->initialized) return fail(h, LBM_ERR_STATE, "rereference before init");
+  if (h->cfg.precision != LBM_FP32_DEV) return LBM_OK;
+  h->adj.ready = false;
+  hipError_t e = pplbm::launch_reref(h->prm, state_ptr(h, h->cur), state_ptr(h, 1 - h->cur), h->buf.mask, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "rereference launch");
+  return LBM_OK;
+}
+
 int lbm_state_ptr(const lbm_lattice* h, void** f) {
   if (!h || !f) return LBM_ERR_INVALID_ARG;
   *f = h->cur == 0 ? h->buf.f_a : h->buf.f_b;
@@ -496,7 +513,7 @@ int lbm_state_ptr(const lbm_lattice* h, void** f) {
 int lbm_get_state(lbm_lattice* h, void* dst) {
   if (!h || !dst) return LBM_ERR_INVALID_ARG;
   if (!h->initialized) return fail(h, LBM_ERR_STATE, "get_state before init");
-  size_t bytes = (size_t)9 * h->cfg.nx * h->cfg.ny * elem_size(&h->cfg);
+  size_t bytes = state_bytes_of(&h->cfg);
   hipError_t e = hipMemcpyAsync(dst, state_ptr(h, h->cur), bytes, hipMemcpyDeviceToDevice, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "state copy");
   return LBM_OK;
@@ -504,7 +521,7 @@ int lbm_get_state(lbm_lattice* h, void* dst) {
 
 int lbm_set_state(lbm_lattice* h, const void* src, int64_t step) {
   if (!h || !src || step < 0) return LBM_ERR_INVALID_ARG;
-  size_t bytes = (size_t)9 * h->cfg.nx * h->cfg.ny * elem_size(&h->cfg);
+  size_t bytes = state_bytes_of(&h->cfg);
   hipError_t e = hipMemcpyAsync(h->buf.f_a, src, bytes, hipMemcpyDeviceToDevice, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "state copy");
   e = hipMemcpyAsync(h->buf.f_b, src, bytes, hipMemcpyDeviceToDevice, h->stream);

@@ -48,6 +48,7 @@ namespace pplbm_host {
 
 size_t align256(size_t v);
 size_t elem_size(const lbm_config* c);
+size_t state_bytes_of(const lbm_config* c);
 int fail(lbm_lattice* h, int code, const std::string& msg);
 int hip_fail(lbm_lattice* h, hipError_t e, const char* what);
 bool config_ok(const lbm_config* c, std::string& why);

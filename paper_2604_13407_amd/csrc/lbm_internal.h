@@ -37,6 +37,9 @@ template <class S>
 hipError_t launch_fields(const StepParams& p, const void* f, const uint8_t* mask, const double* wall_u, void* psi,
                          double* rho, double* ux, double* uy, double* fx, double* fy, double* psi_o,
                          double* partials, int reduce, hipStream_t s);
+// Float storage: the reference density of every node becomes its current
+// density (both population arrays hold the current state).
+hipError_t launch_reref(const StepParams& p, void* fa, void* fb, const uint8_t* mask, hipStream_t s);
 hipError_t launch_finalize(const double* partials, int n_parts, double* out, hipStream_t s);
 
 }  // namespace pplbm

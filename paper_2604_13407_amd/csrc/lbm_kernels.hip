@@ -50,14 +50,50 @@ __global__ void init_kernel(StepParams p, const double* __restrict__ rho0, const
   double u = ux0 ? ux0[k] : 0.0;
   double v = uy0 ? uy0[k] : 0.0;
   double usq = u * u + v * v;
+  // float storage: the node's reference offset c = rhat - rho_ref, rhat the
+  // initial density (as a float)
+  double c = 0.0;
+  if constexpr (sizeof(S) == 4) {
+    const float cf = (float)(r - p.rho_ref);
+    fa[9 * plane + k] = cf;
+    fb[9 * plane + k] = cf;
+    c = (double)cf;
+  }
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     double eu = ex(i) * u + ey(i) * v;
-    // f_eq - w rho_ref = w [(rho - rho_ref) + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u^2)]
-    double dv = wgt(i) * ((r - p.rho_ref) + r * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq));
+    // f_eq - w (rho_ref + c) = w [(rho - rho_ref - c) + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u^2)]
+    double dv = wgt(i) * ((r - p.rho_ref - c) + r * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq));
     fa[(size_t)i * plane + k] = (S)dv;
     fb[(size_t)i * plane + k] = (S)dv;
   }
+}
+
+// Re-reference (float storage): the node's reference density becomes the
+// density of its current post-collision populations; the stored populations
+// are shifted by w_i times the change.  The state is unchanged up to one
+// rounding per population.
+__global__ void reref_kernel(StepParams p, float* __restrict__ fa, float* __restrict__ fb, const uint8_t* mask) {
+  int x = blockIdx.x * blockDim.x + threadIdx.x;
+  int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= p.nx || y >= p.ny) return;
+  const size_t plane = (size_t)p.nx * p.ny;
+  const size_t k = (size_t)y * p.nx + x;
+  if (mask && mask[k]) return;
+  const double c = (double)fa[9 * plane + k];
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) s += (double)fa[(size_t)i * plane + k];
+  const float cn = (float)(c + s);
+  const double dc = c - (double)cn;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const float v = (float)((double)fa[(size_t)i * plane + k] + wgt(i) * dc);
+    fa[(size_t)i * plane + k] = v;
+    fb[(size_t)i * plane + k] = v;
+  }
+  fa[9 * plane + k] = cn;
+  fb[9 * plane + k] = cn;
 }
 
 // ------------------------------------------------------------------ two-pass: psi
@@ -134,8 +170,9 @@ __global__ void collide_kernel(StepParams p, const S* __restrict__ f, S* __restr
                  psi_at(p, psi, mask, x - 1, y - 1), psi_at(p, psi, mask, x + 1, y - 1), Sx, Sy);
     NodeMacro mac = collide_node(p, d, drho, jx, jy, psi[k], Sx, Sy);
     const size_t plane = (size_t)p.nx * p.ny;
+    const double c = ref_offset<S>(f, plane, k);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) fo[(size_t)i * plane + k] = (S)d[i];
+    for (int i = 0; i < 9; ++i) fo[(size_t)i * plane + k] = store_value<S>(d[i], wgt(i), c);
     if (REDUCE) {
       bool bad;
       double rho = p.rho_ref + drho;
@@ -279,8 +316,9 @@ __global__ __launch_bounds__(256) void fused_kernel(StepParams p, const S* __res
       stencil_sums(pE, psn, pW, psm, pNE, pNW, pSW, pSE, Sx, Sy);
       NodeMacro mac = collide_node(p, dc, drc, jxc, jyc, psc, Sx, Sy);
       const size_t k = (size_t)y * p.nx + x;
+      const double c = ref_offset<S>(f, plane, k);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) fo[(size_t)i * plane + k] = (S)dc[i];
+      for (int i = 0; i < 9; ++i) fo[(size_t)i * plane + k] = store_value<S>(dc[i], wgt(i), c);
       if (REDUCE) {
         acc[RED_WALLX] += wallc[0];
         acc[RED_WALLY] += wallc[1];
@@ -742,6 +780,26 @@ struct AMarch {
   bool hl;    // lane 0 or lane 63
   int y1;
   unsigned colB[9], colH[9];  // byte offsets of the pulled columns (interior strips)
+  // float storage: the reference plane, and the lane's column for the halo
+  // reference load (lane 0: x0-1, lane 1: x0-2, lane 62: x0+65, lane 63: x0+64)
+  __amdgpu_buffer_rsrc_t ref;
+  unsigned refbytes;
+  ColGeo hc;
+  bool lane0;
+};
+
+// Reference offsets carried with pulled row q (float storage): c of rows
+// q-1, q, q+1 (j = 0, 1, 2) at the lane's column (cm) and at its halo
+// reference column (ch).
+struct RefRows {
+  float cm[3], ch[3];
+};
+
+template <class S>
+struct ASlot {
+  S raw[9];   // the lane's 9 pulled populations (stored values)
+  S rawh[9];  // lanes 0 and 63: those of the halo column
+  RefRows r;  // float storage only
 };
 
 struct ARow {
@@ -752,8 +810,7 @@ struct ARow {
 };
 
 template <class S, bool INTERIOR>
-__device__ inline void aissue_row(const StepParams& p, const AMarch& m, int y, bool live, S raw[9], S rawh[9],
-                                  RowGeo& g) {
+__device__ inline void aissue_row(const StepParams& p, const AMarch& m, int y, bool live, ASlot<S>& sl, RowGeo& g) {
   g = row_geo(p, y);
   unsigned off[9], offh[9];
   if (INTERIOR) {
@@ -774,37 +831,97 @@ __device__ inline void aissue_row(const StepParams& p, const AMarch& m, int y, b
     off[i] = live ? off[i] : m.bytes;
     offh[i] = live ? offh[i] : m.bytes;
   }
-  load_row<S>(m.in, off, raw);
-  load_row<S>(m.in, offh, rawh);
+  load_row<S>(m.in, off, sl.raw);
+  load_row<S>(m.in, offh, sl.rawh);
+  if constexpr (sizeof(S) == 4) {
+    // rows q-1, q, q+1 (a row beyond a wall is only a bounce-back source,
+    // which takes the node's own offset; its value is not used)
+    const unsigned ro[3] = {g.bot, g.own, g.top};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      unsigned om = (live && g.real) ? (ro[j] + m.c.own) * 4u : m.refbytes;
+      unsigned oh = (live && g.real && m.hc.real) ? (ro[j] + m.hc.own) * 4u : m.refbytes;
+      sl.r.cm[j] = BufIO<float>::load(m.ref, om);
+      sl.r.ch[j] = BufIO<float>::load(m.ref, oh);
+    }
+  }
+}
+
+// DPP move of a float: lane l receives lane l-1's v (CTRL 0x138, wave_shr:1)
+// or lane l+1's (0x130, wave_shl:1); a lane without a source lane gets `fill`.
+template <int CTRL>
+__device__ inline float fbits_dpp(float v, float fill) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, fill),
+                                                               __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+
+// Reference offsets of the 9 source nodes of row q's pulled populations: for
+// the lane (c) and, on lanes 0 and 63, for the halo column (chh).  The source
+// of direction i is x - e_i, or the node itself across a wall.
+__device__ inline void source_refs(const AMarch& m, const RowGeo& g, const RefRows& r, float c[9], float chh[9]) {
+  float cw[3], ce[3], h2[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    cw[j] = fbits_dpp<0x138>(r.cm[j], r.ch[j]);  // x - 1 (lane 0: its halo column x0-1)
+    ce[j] = fbits_dpp<0x130>(r.cm[j], r.ch[j]);  // x + 1 (lane 63: x0+64)
+    // lane 0 <- lane 1's halo load (x0-2), lane 63 <- lane 62's (x0+65)
+    h2[j] = fbits_dpp<0x138>(r.ch[j], fbits_dpp<0x130>(r.ch[j], r.ch[j]));
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int exi = ex(i), eyi = ey(i);
+    const int j = 1 - eyi;
+    const bool wall = (eyi == 1 && g.wall_b) || (eyi == -1 && g.wall_t) || (exi == 1 && m.c.wall_l) ||
+                      (exi == -1 && m.c.wall_r);
+    const float src = exi == 1 ? cw[j] : (exi == -1 ? ce[j] : r.cm[j]);
+    c[i] = wall ? r.cm[1] : src;
+    const bool wallh = (eyi == 1 && g.wall_b) || (eyi == -1 && g.wall_t) || (exi == 1 && m.h.wall_l) ||
+                       (exi == -1 && m.h.wall_r);
+    // halo column x0-1 (lane 0): sources x0-2, x0-1, x0; x0+64 (lane 63): x0+63, x0+64, x0+65
+    const bool far = (exi == 1) == m.lane0;
+    const float hs = exi == 0 ? r.ch[j] : (far ? h2[j] : r.cm[j]);
+    chh[i] = wallh ? r.ch[1] : hs;
+  }
 }
 
 template <class S>
-__device__ inline void arow_state(const StepParams& p, const AMarch& m, const S raw[9], const S rawh[9], ARow& t) {
+__device__ inline void arow_state(const StepParams& p, const AMarch& m, const ASlot<S>& sl, ARow& t) {
   double d[9];
+  double h = 0.0;
+  if constexpr (sizeof(S) == 4) {
+    float c[9], chh[9];
+    source_refs(m, t.g, sl.r, c, chh);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) d[i] = (double)raw[i];
+    for (int i = 0; i < 9; ++i) {
+      d[i] = (double)sl.raw[i] + wgt(i) * (double)c[i];
+      h += (double)sl.rawh[i] + wgt(i) * (double)chh[i];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      d[i] = (double)sl.raw[i];
+      h += (double)sl.rawh[i];
+    }
+  }
   node_sums(d, t.drho, t.jx, t.jy);
   bool bad;
   const double ps = psi_of(p, p.rho_ref + t.drho, bad);
   t.psi = t.g.real ? ps : p.psi_solid;
   t.bad = t.g.real && bad;
-  double h = 0.0;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) h += (double)rawh[i];
   bool badh;
   const double psh = psi_of(p, p.rho_ref + h, badh);
   t.psih = (t.g.real && m.h.real) ? psh : p.psi_solid;
 }
 
-// Collide and store row y (`cur0`, `t0`), with psi of rows y-1 (`tm`) and
-// y+1 (`t1`, finished here from `cur1`); the loads of row y + AHEAD go into
-// `nxt` first.
+// Collide and store row y (slot `s0`, state `t0`), with psi of rows y-1 (`tm`)
+// and y+1 (`t1`, finished here from slot `s1`); the loads of row y + AHEAD
+// go into slot `sn` first.
 template <class S, bool REDUCE, bool INTERIOR, int AHEAD>
-__device__ inline void amarch_row(const StepParams& p, const AMarch& m, int y, const S cur0[9], const S cur1[9],
-                                  const S cur1h[9], S nxt[9], S nxth[9], const ARow& tm, const ARow& t0, ARow& t1,
+__device__ inline void amarch_row(const StepParams& p, const AMarch& m, int y, const ASlot<S>& s0,
+                                  const ASlot<S>& s1, ASlot<S>& sn, const ARow& tm, const ARow& t0, ARow& t1,
                                   ARow& tn, double* acc) {
-  aissue_row<S, INTERIOR>(p, m, y + AHEAD, y + AHEAD <= m.y1, nxt, nxth, tn.g);
-  arow_state<S>(p, m, cur1, cur1h, t1);
+  aissue_row<S, INTERIOR>(p, m, y + AHEAD, y + AHEAD <= m.y1, sn, tn.g);
+  arow_state<S>(p, m, s1, t1);
   // lane 0's west and lane 63's east neighbours are the halo columns, whose
   // psi those two lanes hold in psih
   const double pW = wave_shr1_fill(t0.psi, t0.psih);
@@ -814,16 +931,29 @@ __device__ inline void amarch_row(const StepParams& p, const AMarch& m, int y, c
   const double pNW = wave_shr1_fill(t1.psi, t1.psih);
   const double pNE = wave_shl1_fill(t1.psi, t1.psih);
   double d[9];
+  double c_own = 0.0;
+  if constexpr (sizeof(S) == 4) {
+    float c[9], chh[9];
+    source_refs(m, t0.g, s0.r, c, chh);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) d[i] = (double)cur0[i];
+    for (int i = 0; i < 9; ++i) d[i] = (double)s0.raw[i] + wgt(i) * (double)c[i];
+    c_own = (double)s0.r.cm[1];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) d[i] = (double)s0.raw[i];
+  }
   double Sx, Sy;
   stencil_sums(pE, t1.psi, pW, tm.psi, pNE, pNW, pSW, pSE, Sx, Sy);
+  double dw[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) dw[i] = d[i];
   NodeMacro mac = collide_node(p, d, t0.drho, t0.jx, t0.jy, t0.psi, Sx, Sy);
   const bool store = t0.g.real;
   const unsigned k = t0.g.own + m.c.own;
 #pragma unroll
   for (int i = 0; i < 9; ++i)
-    BufIO<S>::store((S)d[i], m.out, store ? ((unsigned)i * m.N + k) * (unsigned)sizeof(S) : m.bytes);
+    BufIO<S>::store(store_value<S>(d[i], wgt(i), c_own), m.out,
+                    store ? ((unsigned)i * m.N + k) * (unsigned)sizeof(S) : m.bytes);
   if (REDUCE && store) {
     if (!INTERIOR) {
       double wx = 0.0, wy = 0.0;
@@ -833,7 +963,8 @@ __device__ inline void amarch_row(const StepParams& p, const AMarch& m, int y, c
         const bool wall = (eyi == 1 && t0.g.wall_b) || (eyi == -1 && t0.g.wall_t) || (exi == 1 && m.c.wall_l) ||
                           (exi == -1 && m.c.wall_r);
         if (wall) {
-          double both = 2.0 * ((double)cur0[i] + wgt(i) * p.rho_ref);
+          // the pulled deviation at a wall link is the node's own opposite population
+          double both = 2.0 * (dw[i] + wgt(i) * p.rho_ref);
           wx -= exi * both;
           wy -= eyi * both;
         }
@@ -850,39 +981,39 @@ __device__ inline void amarch_row(const StepParams& p, const AMarch& m, int y, c
 template <class S, bool REDUCE, bool INTERIOR>
 __device__ inline void amarch(const StepParams& p, const AMarch& m, int y0, double* acc) {
   if (sizeof(S) == 4) {
-    S ra[9], rb[9], rc[9], ha[9], hb[9], hc[9];
+    ASlot<S> sa, sb, sc;
     ARow ta, tb, tc;
     // row r lives in slot (r - y0 + 1) mod 3: y0-1 -> c, y0 -> a, y0+1 -> b
-    aissue_row<S, INTERIOR>(p, m, y0 - 1, true, rc, hc, tc.g);
-    aissue_row<S, INTERIOR>(p, m, y0, true, ra, ha, ta.g);
-    aissue_row<S, INTERIOR>(p, m, y0 + 1, true, rb, hb, tb.g);
-    arow_state<S>(p, m, rc, hc, tc);
-    arow_state<S>(p, m, ra, ha, ta);
+    aissue_row<S, INTERIOR>(p, m, y0 - 1, true, sc, tc.g);
+    aissue_row<S, INTERIOR>(p, m, y0, true, sa, ta.g);
+    aissue_row<S, INTERIOR>(p, m, y0 + 1, true, sb, tb.g);
+    arow_state<S>(p, m, sc, tc);
+    arow_state<S>(p, m, sa, ta);
     for (int y = y0; y < m.y1; y += 3) {
-      amarch_row<S, REDUCE, INTERIOR, 2>(p, m, y, ra, rb, hb, rc, hc, tc, ta, tb, tc, acc);
+      amarch_row<S, REDUCE, INTERIOR, 2>(p, m, y, sa, sb, sc, tc, ta, tb, tc, acc);
       if (y + 1 >= m.y1) break;
-      amarch_row<S, REDUCE, INTERIOR, 2>(p, m, y + 1, rb, rc, hc, ra, ha, ta, tb, tc, ta, acc);
+      amarch_row<S, REDUCE, INTERIOR, 2>(p, m, y + 1, sb, sc, sa, ta, tb, tc, ta, acc);
       if (y + 2 >= m.y1) break;
-      amarch_row<S, REDUCE, INTERIOR, 2>(p, m, y + 2, rc, ra, ha, rb, hb, tb, tc, ta, tb, acc);
+      amarch_row<S, REDUCE, INTERIOR, 2>(p, m, y + 2, sc, sa, sb, tb, tc, ta, tb, acc);
     }
   } else {
-    S r0[9], r1[9], r2[9], r3[9], h0[9], h1[9], h2[9], h3[9];
+    ASlot<S> s0, s1, s2, s3;
     ARow t0, t1, t2, t3;
     // row r lives in slot (r - y0 + 1) mod 4: y0-1 -> 0, y0 -> 1, y0+1 -> 2, y0+2 -> 3
-    aissue_row<S, INTERIOR>(p, m, y0 - 1, true, r0, h0, t0.g);
-    aissue_row<S, INTERIOR>(p, m, y0, true, r1, h1, t1.g);
-    aissue_row<S, INTERIOR>(p, m, y0 + 1, true, r2, h2, t2.g);
-    aissue_row<S, INTERIOR>(p, m, y0 + 2, y0 + 2 <= m.y1, r3, h3, t3.g);
-    arow_state<S>(p, m, r0, h0, t0);
-    arow_state<S>(p, m, r1, h1, t1);
+    aissue_row<S, INTERIOR>(p, m, y0 - 1, true, s0, t0.g);
+    aissue_row<S, INTERIOR>(p, m, y0, true, s1, t1.g);
+    aissue_row<S, INTERIOR>(p, m, y0 + 1, true, s2, t2.g);
+    aissue_row<S, INTERIOR>(p, m, y0 + 2, y0 + 2 <= m.y1, s3, t3.g);
+    arow_state<S>(p, m, s0, t0);
+    arow_state<S>(p, m, s1, t1);
     for (int y = y0; y < m.y1; y += 4) {
-      amarch_row<S, REDUCE, INTERIOR, 3>(p, m, y, r1, r2, h2, r0, h0, t0, t1, t2, t0, acc);
+      amarch_row<S, REDUCE, INTERIOR, 3>(p, m, y, s1, s2, s0, t0, t1, t2, t0, acc);
       if (y + 1 >= m.y1) break;
-      amarch_row<S, REDUCE, INTERIOR, 3>(p, m, y + 1, r2, r3, h3, r1, h1, t1, t2, t3, t1, acc);
+      amarch_row<S, REDUCE, INTERIOR, 3>(p, m, y + 1, s2, s3, s1, t1, t2, t3, t1, acc);
       if (y + 2 >= m.y1) break;
-      amarch_row<S, REDUCE, INTERIOR, 3>(p, m, y + 2, r3, r0, h0, r2, h2, t2, t3, t0, t2, acc);
+      amarch_row<S, REDUCE, INTERIOR, 3>(p, m, y + 2, s3, s0, s2, t2, t3, t0, t2, acc);
       if (y + 3 >= m.y1) break;
-      amarch_row<S, REDUCE, INTERIOR, 3>(p, m, y + 3, r0, r1, h1, r3, h3, t3, t0, t1, t3, acc);
+      amarch_row<S, REDUCE, INTERIOR, 3>(p, m, y + 3, s0, s1, s3, t3, t0, t1, t3, acc);
     }
   }
 }
@@ -936,6 +1067,7 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
   m.out = __builtin_amdgcn_make_buffer_rsrc((void*)fo, (short)0, (int)m.bytes, 0x00020000);
   const int x0 = strip * WAVE;
   m.hl = lane == 0 || lane == WAVE - 1;
+  m.lane0 = lane == 0;
   m.c = col_geo(p, x0 + lane, true);
   m.h = col_geo(p, lane == 0 ? x0 - 1 : x0 + WAVE, m.hl);
 #pragma unroll
@@ -943,6 +1075,13 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
     const int exi = ex(i);
     m.colB[i] = (exi == 1 ? m.c.left : (exi == -1 ? m.c.right : m.c.own)) * (unsigned)sizeof(S);
     m.colH[i] = (exi == 1 ? m.h.left : (exi == -1 ? m.h.right : m.h.own)) * (unsigned)sizeof(S);
+  }
+  if constexpr (sizeof(S) == 4) {
+    // the reference plane follows the 9 population planes
+    m.refbytes = m.N * 4u;
+    m.ref = __builtin_amdgcn_make_buffer_rsrc((void*)(f + (size_t)9 * m.N), (short)0, (int)m.refbytes, 0x00020000);
+    const int xr = lane == 0 ? x0 - 1 : lane == 1 ? x0 - 2 : lane == WAVE - 2 ? x0 + WAVE + 1 : x0 + WAVE;
+    m.hc = col_geo(p, xr, lane <= 1 || lane >= WAVE - 2);
   }
   const int y0 = seg * seg_len;
   m.y1 = min(y0 + seg_len, p.ny);
@@ -1014,6 +1153,31 @@ hipError_t launch_init(const StepParams& p, const double* rho0, const double* ux
   return hipGetLastError();
 }
 
+// The 62-column strip kernel: double storage only (float storage keeps a
+// per-node reference plane, which the aligned kernel and the general fused
+// kernel read).  Returns false when it does not apply.
+template <class S>
+static bool launch_fast62(const StepParams& p, const StepLaunch& L, hipStream_t st) {
+  if constexpr (sizeof(S) != 8) {
+    return false;
+  } else {
+    const S* f = (const S*)L.f_in;
+    S* fo = (S*)L.f_out;
+    int n_strips, n_segs;
+    fused_shape(p.nx, p.ny, L.seg_len, false, &n_strips, &n_segs);
+    int groups = (n_strips + 3) / 4;
+    int total = groups * n_segs;
+    int per_xcd = (total + 7) / 8;
+    if (L.reduce)
+      hipLaunchKernelGGL((fast_kernel<S, true>), dim3(8 * per_xcd), dim3(256), 0, st, p, f, fo, n_strips, L.seg_len,
+                         n_segs, groups, per_xcd, L.partials);
+    else
+      hipLaunchKernelGGL((fast_kernel<S, false>), dim3(8 * per_xcd), dim3(256), 0, st, p, f, fo, n_strips,
+                         L.seg_len, n_segs, groups, per_xcd, L.partials);
+    return true;
+  }
+}
+
 template <class S>
 hipError_t launch_step(const StepParams& p, const StepLaunch& L, hipStream_t st) {
   const S* f = (const S*)L.f_in;
@@ -1040,18 +1204,8 @@ hipError_t launch_step(const StepParams& p, const StepLaunch& L, hipStream_t st)
     else
       hipLaunchKernelGGL((aligned_kernel<S, false>), dim3(8 * per_xcd), dim3(256), 0, st, p, f, fo, n_strips,
                          L.seg_len, n_segs, groups, per_xcd, L.partials);
-  } else if (L.fast) {
-    int n_strips, n_segs;
-    fused_shape(p.nx, p.ny, L.seg_len, false, &n_strips, &n_segs);
-    int groups = (n_strips + 3) / 4;
-    int total = groups * n_segs;
-    int per_xcd = (total + 7) / 8;
-    if (L.reduce)
-      hipLaunchKernelGGL((fast_kernel<S, true>), dim3(8 * per_xcd), dim3(256), 0, st, p, f, fo, n_strips, L.seg_len,
-                         n_segs, groups, per_xcd, L.partials);
-    else
-      hipLaunchKernelGGL((fast_kernel<S, false>), dim3(8 * per_xcd), dim3(256), 0, st, p, f, fo, n_strips, L.seg_len,
-                         n_segs, groups, per_xcd, L.partials);
+  } else if (L.fast && launch_fast62<S>(p, L, st)) {
+    // launched: the 62-column strip kernel (double storage, widths not a multiple of 64)
   } else {
     int n_strips, n_segs;
     fused_shape(p.nx, p.ny, L.seg_len, false, &n_strips, &n_segs);
@@ -1064,6 +1218,12 @@ hipError_t launch_step(const StepParams& p, const StepLaunch& L, hipStream_t st)
       hipLaunchKernelGGL((fused_kernel<S, false>), dim3(blocks), dim3(256), 0, st, p, f, fo, L.mask, L.wall_u,
                          n_strips, L.seg_len, n_segs, L.partials);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_reref(const StepParams& p, void* fa, void* fb, const uint8_t* mask, hipStream_t st) {
+  dim3 blk(64, 4);
+  hipLaunchKernelGGL(reref_kernel, node_grid(p, blk), blk, 0, st, p, (float*)fa, (float*)fb, mask);
   return hipGetLastError();
 }
 

@@ -1,10 +1,17 @@
 // Node-level device arithmetic of one D2Q9 pseudopotential MRT step.
 //
-// Storage convention: populations are kept as deviations d_i = f_i - w_i rho_ref
-// in the storage type S (float or double).  The FP64 path uses rho_ref = 0,
-// so d_i = f_i.  Since M (w_i rho_ref) = rho_ref (1, -2, 1, 0, 0, 0, 0, 0, 0),
-// the collision acts on deviation moments with m^eq shifted by the same
-// vector; all other terms are unchanged.
+// Arithmetic convention: the step works on deviations d_i = f_i - w_i R with
+// a uniform R (rho_ref; 0 for double storage, so d_i = f_i).  Since
+// M (w_i R) = R (1, -2, 1, 0, 0, 0, 0, 0, 0), the collision acts on deviation
+// moments with m^eq shifted by the same vector; all other terms are unchanged.
+//
+// Storage convention: double storage keeps d_i.  Float storage keeps
+// s_i(x) = f_i(x) - w_i rhat(x) = d_i(x) - w_i c(x) with a per-node reference
+// density rhat(x) = R + c(x), the offset c held as a tenth float plane of the
+// population array (the initial density, unless re-referenced).  Deviations
+// from the node's own reference stay small in liquid and vapour alike, so the
+// one rounding per stored population is small wherever the density has not
+// moved far from the reference.
 //
 // Arithmetic is double for both storage types: loads are widened, the step is
 // computed in double and each population is rounded once when stored.  In
@@ -111,6 +118,33 @@ __host__ __device__ inline bool solid_at(const StepParams& p, const uint8_t* __r
   return mask ? (mask[(size_t)y * p.nx + x] != 0) : false;
 }
 
+// Planes of a population array: 9 populations, plus the reference plane c for
+// float storage.
+template <class S>
+__host__ __device__ constexpr int state_planes() {
+  return sizeof(S) == 4 ? 10 : 9;
+}
+
+// The reference offset c(k) of node k (0 for double storage).
+template <class S>
+__host__ __device__ inline double ref_offset(const S* __restrict__ f, size_t plane, size_t k) {
+  if constexpr (sizeof(S) == 4) {
+    return (double)f[9 * plane + k];
+  } else {
+    return 0.0;
+  }
+}
+
+// Stored value of a post-collision deviation d at a node with offset c.
+template <class S>
+__host__ __device__ inline S store_value(double d, double w, double c) {
+  if constexpr (sizeof(S) == 4) {
+    return (S)(d - w * c);
+  } else {
+    return (S)d;
+  }
+}
+
 // Pull streaming (Eq. 2b) with halfway bounce-back: d[i] = dbar_i(x - e_i), or
 // dbar_opp(i)(x) (+ the moving-wall term) when x - e_i is solid.  When
 // `wall` is non-null, accumulates the momentum handed to the walls.
@@ -119,7 +153,8 @@ __host__ __device__ inline void pull_node(const StepParams& p, const S* __restri
                                           const double* __restrict__ wall_u, int x, int y, double d[9], double* wall) {
   const size_t plane = (size_t)p.nx * p.ny;
   const size_t self = (size_t)y * p.nx + x;
-  d[0] = (double)f[self];
+  const double c_self = ref_offset<S>(f, plane, self);
+  d[0] = (double)f[self] + wgt(0) * c_self;
   double rho_w = 0.0;
   bool have_rho_w = false;
 #pragma unroll
@@ -128,9 +163,10 @@ __host__ __device__ inline void pull_node(const StepParams& p, const S* __restri
     bool inside;
     bool sol = solid_at(p, mask, x - ex(i), y - ey(i), xs, ys, inside);
     if (!sol) {
-      d[i] = (double)f[(size_t)i * plane + (size_t)ys * p.nx + xs];
+      const size_t ks = (size_t)ys * p.nx + xs;
+      d[i] = (double)f[(size_t)i * plane + ks] + wgt(i) * ref_offset<S>(f, plane, ks);
     } else {
-      double v = (double)f[(size_t)opp(i) * plane + self];
+      double v = (double)f[(size_t)opp(i) * plane + self] + wgt(i) * c_self;
       double mw = 0.0;
       if (wall_u && inside) {
         if (!have_rho_w) {
@@ -138,7 +174,7 @@ __host__ __device__ inline void pull_node(const StepParams& p, const S* __restri
           double s = 0.0;
 #pragma unroll
           for (int q = 0; q < 9; ++q) s += (double)f[(size_t)q * plane + self];
-          rho_w = p.rho_ref + s;
+          rho_w = p.rho_ref + c_self + s;
           have_rho_w = true;
         }
         size_t ks = (size_t)ys * p.nx + xs;

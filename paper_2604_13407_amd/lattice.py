@@ -37,7 +37,7 @@ EXPORTS = ("lbm_abi_version", "lbm_state_bytes", "lbm_workspace_bytes", "lbm_cre
            "lbm_set_body_force", "lbm_set_phase_densities", "lbm_set_walls", "lbm_init_equilibrium", "lbm_step",
            "lbm_set_rows_per_wave",
            "lbm_step_count", "lbm_read_fields", "lbm_reduce", "lbm_state_ptr", "lbm_get_state", "lbm_set_state",
-           "lbm_adjoint_workspace_bytes", "lbm_adjoint_forward", "lbm_adjoint_backward")
+           "lbm_rereference", "lbm_adjoint_workspace_bytes", "lbm_adjoint_forward", "lbm_adjoint_backward")
 
 
 class LbmError(RuntimeError):
@@ -105,6 +105,7 @@ def lib():
         L.lbm_state_ptr.argtypes = [vp, C.POINTER(vp)]
         L.lbm_get_state.argtypes = [vp, vp]
         L.lbm_set_state.argtypes = [vp, vp, C.c_int64]
+        L.lbm_rereference.argtypes = [vp]
         L.lbm_adjoint_workspace_bytes.argtypes = [C.POINTER(Config), C.POINTER(AdjointConfig), C.POINTER(C.c_size_t)]
         L.lbm_adjoint_forward.argtypes = [vp, C.POINTER(AdjointConfig), vp, vp, C.c_size_t, dp]
         L.lbm_adjoint_backward.argtypes = [vp, vp, dp, dp]
@@ -142,8 +143,10 @@ class Lattice:
         self._check(L.lbm_state_bytes(C.byref(self.cfg), C.byref(sb)), None)
         self._check(L.lbm_workspace_bytes(C.byref(self.cfg), C.byref(wb)), None)
         self.dtype = torch.float64 if precision == FP64 else torch.float32
-        self.f_a = torch.empty((9, ny, nx), dtype=self.dtype, device=self.device)
-        self.f_b = torch.empty((9, ny, nx), dtype=self.dtype, device=self.device)
+        # 9 population planes; float storage adds the per-node reference plane
+        planes = sb.value // (nx * ny * (8 if precision == FP64 else 4))
+        self.f_a = torch.empty((planes, ny, nx), dtype=self.dtype, device=self.device)
+        self.f_b = torch.empty((planes, ny, nx), dtype=self.dtype, device=self.device)
         assert self.f_a.numel() * self.f_a.element_size() == sb.value
         # torch's caching allocator returns >= 512-byte aligned blocks
         self.workspace = torch.empty(wb.value, dtype=torch.uint8, device=self.device)
@@ -239,8 +242,13 @@ class Lattice:
         self._check(lib().lbm_step_count(self.h, C.byref(v)), self.h)
         return v.value
 
+    def rereference(self):
+        """Float storage: make every node's reference density its current density."""
+        self._check(lib().lbm_rereference(self.h), self.h)
+
     def state(self) -> torch.Tensor:
-        """The population array that holds the current state (deviations in FP32_DEV)."""
+        """The array that holds the current state: 9 population planes (FP32_DEV: stored
+        relative to each node's reference density, which is the tenth plane)."""
         p = C.c_void_p(0)
         self._check(lib().lbm_state_ptr(self.h, C.byref(p)), self.h)
         return self.f_a if p.value == self.f_a.data_ptr() else self.f_b

@@ -38,7 +38,8 @@ def cfg(**kw):
 def test_sizes_and_config_validation():
     L = LT.lib()
     b = C.c_size_t(0)
-    assert L.lbm_state_bytes(C.byref(cfg()), C.byref(b)) == 0 and b.value == 9 * 64 * 32 * 4
+    # float storage: 9 population planes and the per-node reference plane
+    assert L.lbm_state_bytes(C.byref(cfg()), C.byref(b)) == 0 and b.value == 10 * 64 * 32 * 4
     assert L.lbm_state_bytes(C.byref(cfg(precision=LT.FP64)), C.byref(b)) == 0 and b.value == 9 * 64 * 32 * 8
     assert L.lbm_workspace_bytes(C.byref(cfg()), C.byref(b)) == 0 and b.value % 256 == 0 and b.value > 64 * 32 * 4
     for bad in (dict(nx=0), dict(ny=-3), dict(precision=7), dict(kernel=5), dict(log_capacity=0),
@@ -90,6 +91,7 @@ def test_setters_validate_and_state_errors_without_a_gpu():
         r = LT.Reduction()
         assert L.lbm_reduce(h, C.byref(r)) == -6
         assert L.lbm_get_state(h, C.c_void_p(0x5000)) == -6
+        assert L.lbm_rereference(h) == -6
         assert L.lbm_init_equilibrium(h, None, None, None) == -1
         assert "NULL" in L.lbm_last_error(h).decode()
         n = C.c_int64(-1)
@@ -118,9 +120,9 @@ def test_adjoint_workspace_size_and_validation():
     c = cfg()
     n = 64 * 32
     assert L.lbm_adjoint_workspace_bytes(C.byref(c), C.byref(acfg()), C.byref(b)) == 0
-    # 4 checkpoints (steps 0, 30, 60, 90) + 2 replay arrays of FP32 populations, 30 trajectory
-    # slots of 4 doubles, adjoint fields of 18 floats and 5 doubles per node
-    assert b.value >= (4 + 2) * 9 * n * 4 + 30 * 4 * n * 8 + (18 * 4 + 5 * 8) * n
+    # 4 checkpoints (steps 0, 30, 60, 90) + 2 replay arrays of FP32 states (10 planes), 30
+    # trajectory slots of 4 doubles, adjoint fields of 18 floats and 5 doubles per node
+    assert b.value >= (4 + 2) * 10 * n * 4 + 30 * 4 * n * 8 + (18 * 4 + 5 * 8) * n
     assert b.value % 256 == 0
     small = b.value
     assert L.lbm_adjoint_workspace_bytes(C.byref(c), C.byref(acfg(checkpoint_every=10)), C.byref(b)) == 0

@@ -60,7 +60,7 @@ def crop_oracle(w, steps, x0, x1, y0, y1):
     return {k: mac[k][sy:sy + (y1 - y0), sx:sx + (x1 - x0)] for k in ("rho", "ux", "uy", "fintx", "finty", "psi")}
 
 
-def check(w, g, o, x0, x1, y0, y1, precision, scale_u):
+def check(w, g, o, x0, x1, y0, y1, precision, scale_u, tol64=1e-12):
     mask = w.mask()
     fl = np.ones((y1 - y0, x1 - x0), bool) if mask is None else (mask[y0:y1, x0:x1] == 0)
     gw = {k: g[k][y0:y1, x0:x1] for k in o}
@@ -69,7 +69,7 @@ def check(w, g, o, x0, x1, y0, y1, precision, scale_u):
         for k in ("rho", "ux", "uy", "psi"):
             sc = max(scale_u, U_FLOOR) if k in ("ux", "uy") else np.max(np.abs(o[k][fl]))
             err = np.max(np.abs(gw[k][fl] - o[k][fl])) / sc
-            assert err <= 1e-12, (w.name, k, err)
+            assert err <= tol64, (w.name, k, err)
     else:
         rerr = np.max(np.abs(gw["rho"][fl] - o["rho"][fl]) / o["rho"][fl])
         uerr = max(np.max(np.abs(gw["ux"][fl] - o["ux"][fl])), np.max(np.abs(gw["uy"][fl] - o["uy"][fl]))) / scale_u
@@ -125,3 +125,32 @@ def test_sampled_windows_at_full_size(name, make, steps, windows, precision):
         else:
             o = crop_oracle(w, steps, x0, x1, y0, y1)
         check(w, g, o, x0, x1, y0, y1, precision, scale_u)
+
+
+@pytest.fixture(scope="module")
+def aligned_full_oracle():
+    """The grid-aligned two-phase Poiseuille (4 x 100) run to its full 20,000 steps by the
+    oracle, original and improved schemes."""
+    out = {}
+    for scheme in (WL.SCHEME_ORIGINAL, WL.SCHEME_IMPROVED):
+        w = WL.poiseuille_aligned(scheme=scheme)
+        print(f"[fullsize] oracle aligned Poiseuille scheme={scheme} {w.steps} steps", flush=True)
+        o = O.Oracle(oracle_params(w)).init(w.rho0())
+        o.step(w.steps)
+        om = o.macros()
+        out[scheme] = {k: om[k] for k in ("rho", "ux", "uy", "fintx", "finty", "psi")}
+    return out
+
+
+@pytest.mark.parametrize("precision", [LT.FP32_DEV, LT.FP64])
+@pytest.mark.parametrize("scheme", [WL.SCHEME_ORIGINAL, WL.SCHEME_IMPROVED])
+def test_aligned_poiseuille_full_run(scheme, precision, aligned_full_oracle):
+    """All 20,000 steps of the grid-aligned channel, both schemes, whole lattice.  Two
+    double-precision runs that round differently (fused multiply-adds and summation
+    order on the GPU, none in the oracle) drift apart by about steps x eps (measured
+    1e-11 here); the FP64 bar is 1e-12 per 100 steps, 2e-10 for this run."""
+    w = WL.poiseuille_aligned(scheme=scheme)
+    lat, g = run_gpu(w, w.steps, precision)
+    o = aligned_full_oracle[scheme]
+    scale_u = max(np.max(np.abs(o["ux"])), np.max(np.abs(o["uy"])))
+    check(w, g, o, 0, w.nx, 0, w.ny, precision, scale_u, tol64=1e-12 * w.steps / 100)

@@ -285,3 +285,29 @@ def test_rows_per_wave_do_not_change_results(precision, make):
         assert torch.equal(s, states[0])
         for a, b in zip(r, recs[0]):
             assert a["mass"] == pytest.approx(b["mass"], rel=1e-14)
+
+
+@pytest.mark.parametrize("make", [droplet_small, droplet_aligned])
+def test_rereference_keeps_the_run(make):
+    """Float storage: re-referencing every node to its current density changes the
+    stored values but not the run beyond rounding (checked against the FP64 oracle
+    after further steps); it is a no-op for double storage."""
+    w = make()
+    a = LT.Lattice.from_workload(w, precision=LT.FP32_DEV)
+    a.step(30)
+    before = a.state().clone()
+    a.rereference()
+    torch.cuda.synchronize()
+    after = a.state()
+    assert not torch.equal(before[9], after[9])  # the reference plane moved
+    a.step(30)
+    g = gpu_fields(a)
+    o = oracle_for(w)
+    o.step(60)
+    compare_fp32(w, g, o.macros())
+    b = LT.Lattice.from_workload(w, precision=LT.FP64)
+    b.step(5)
+    s = b.state().clone()
+    b.rereference()
+    torch.cuda.synchronize()
+    assert torch.equal(s, b.state())
