@@ -29,8 +29,8 @@ bool aligned_strips(int nx, int fast);
 void fused_shape(int nx, int ny, int seg_len, bool aligned, int* n_strips, int* n_segs);
 
 template <class S>
-hipError_t launch_init(const StepParams& p, const double* rho0, const double* ux0, const double* uy0, void* fa,
-                       void* fb, hipStream_t s);
+hipError_t launch_init(const StepParams& p, const double* rho0, const double* ux0, const double* uy0,
+                       const uint8_t* mask, void* fa, void* fb, hipStream_t s);
 template <class S>
 hipError_t launch_step(const StepParams& p, const StepLaunch& L, hipStream_t s);
 template <class S>

@@ -40,7 +40,8 @@ __device__ inline double wave_sum(double v) {
 // ------------------------------------------------------------------ init
 template <class S>
 __global__ void init_kernel(StepParams p, const double* __restrict__ rho0, const double* __restrict__ ux0,
-                            const double* __restrict__ uy0, S* __restrict__ fa, S* __restrict__ fb) {
+                            const double* __restrict__ uy0, const uint8_t* __restrict__ mask, S* __restrict__ fa,
+                            S* __restrict__ fb) {
   int x = blockIdx.x * blockDim.x + threadIdx.x;
   int y = blockIdx.y * blockDim.y + threadIdx.y;
   if (x >= p.nx || y >= p.ny) return;
@@ -50,50 +51,84 @@ __global__ void init_kernel(StepParams p, const double* __restrict__ rho0, const
   double u = ux0 ? ux0[k] : 0.0;
   double v = uy0 ? uy0[k] : 0.0;
   double usq = u * u + v * v;
-  // float storage: the node's reference offset c = rhat - rho_ref, rhat the
-  // initial density (as a float)
-  double c = 0.0;
+  // float storage: every node's reference offset is c = rhat - rho_ref with
+  // rhat its initial density (as a float); population i is stored relative
+  // to the offset of the node that pulls it (x + e_i, or x across a wall)
+  double cd[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) cd[i] = 0.0;
   if constexpr (sizeof(S) == 4) {
     const float cf = (float)(r - p.rho_ref);
     fa[9 * plane + k] = cf;
     fb[9 * plane + k] = cf;
-    c = (double)cf;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      int xd, yd;
+      bool inside;
+      const bool sol = solid_at(p, mask, x + ex(i), y + ey(i), xd, yd, inside);
+      cd[i] = (double)(sol ? cf : (float)(rho0[(size_t)yd * p.nx + xd] - p.rho_ref));
+    }
   }
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     double eu = ex(i) * u + ey(i) * v;
     // f_eq - w (rho_ref + c) = w [(rho - rho_ref - c) + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u^2)]
-    double dv = wgt(i) * ((r - p.rho_ref - c) + r * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq));
+    double dv = wgt(i) * ((r - p.rho_ref - cd[i]) + r * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq));
     fa[(size_t)i * plane + k] = (S)dv;
     fb[(size_t)i * plane + k] = (S)dv;
   }
 }
 
-// Re-reference (float storage): the node's reference density becomes the
-// density of its current post-collision populations; the stored populations
-// are shifted by w_i times the change.  The state is unchanged up to one
-// rounding per population.
-__global__ void reref_kernel(StepParams p, float* __restrict__ fa, float* __restrict__ fb, const uint8_t* mask) {
+// Re-reference (float storage), three passes over the current array `fa`:
+// the new offset of every fluid node (the density of its current
+// post-collision populations) goes to the reference plane of `fb`; then every
+// stored population moves from its puller's old offset to the new one, in
+// both arrays; then the new plane is copied into `fa`.  The state is
+// unchanged up to one rounding per population.
+__global__ void reref_new_kernel(StepParams p, const float* __restrict__ fa, float* __restrict__ fb,
+                                 const uint8_t* mask) {
+  int x = blockIdx.x * blockDim.x + threadIdx.x;
+  int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= p.nx || y >= p.ny) return;
+  const size_t plane = (size_t)p.nx * p.ny;
+  const size_t k = (size_t)y * p.nx + x;
+  if (mask && mask[k]) {
+    fb[9 * plane + k] = fa[9 * plane + k];
+    return;
+  }
+  double cd[9];
+  dest_refs<float>(p, fa, mask, x, y, cd);
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) s += (double)fa[(size_t)i * plane + k] + wgt(i) * cd[i];
+  fb[9 * plane + k] = (float)s;
+}
+
+__global__ void reref_shift_kernel(StepParams p, float* __restrict__ fa, float* __restrict__ fb, const uint8_t* mask) {
   int x = blockIdx.x * blockDim.x + threadIdx.x;
   int y = blockIdx.y * blockDim.y + threadIdx.y;
   if (x >= p.nx || y >= p.ny) return;
   const size_t plane = (size_t)p.nx * p.ny;
   const size_t k = (size_t)y * p.nx + x;
   if (mask && mask[k]) return;
-  const double c = (double)fa[9 * plane + k];
-  double s = 0.0;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) s += (double)fa[(size_t)i * plane + k];
-  const float cn = (float)(c + s);
-  const double dc = c - (double)cn;
+  double co[9], cn[9];
+  dest_refs<float>(p, fa, mask, x, y, co);
+  dest_refs<float>(p, fb, mask, x, y, cn);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    const float v = (float)((double)fa[(size_t)i * plane + k] + wgt(i) * dc);
+    const float v = (float)((double)fa[(size_t)i * plane + k] + wgt(i) * (co[i] - cn[i]));
     fa[(size_t)i * plane + k] = v;
     fb[(size_t)i * plane + k] = v;
   }
-  fa[9 * plane + k] = cn;
-  fb[9 * plane + k] = cn;
+}
+
+__global__ void reref_copy_kernel(StepParams p, float* __restrict__ fa, const float* __restrict__ fb) {
+  int x = blockIdx.x * blockDim.x + threadIdx.x;
+  int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= p.nx || y >= p.ny) return;
+  const size_t plane = (size_t)p.nx * p.ny;
+  const size_t k = (size_t)y * p.nx + x;
+  fa[9 * plane + k] = fb[9 * plane + k];
 }
 
 // ------------------------------------------------------------------ two-pass: psi
@@ -170,9 +205,10 @@ __global__ void collide_kernel(StepParams p, const S* __restrict__ f, S* __restr
                  psi_at(p, psi, mask, x - 1, y - 1), psi_at(p, psi, mask, x + 1, y - 1), Sx, Sy);
     NodeMacro mac = collide_node(p, d, drho, jx, jy, psi[k], Sx, Sy);
     const size_t plane = (size_t)p.nx * p.ny;
-    const double c = ref_offset<S>(f, plane, k);
+    double cd[9];
+    dest_refs<S>(p, f, mask, x, y, cd);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) fo[(size_t)i * plane + k] = store_value<S>(d[i], wgt(i), c);
+    for (int i = 0; i < 9; ++i) fo[(size_t)i * plane + k] = store_value<S>(d[i], wgt(i), cd[i]);
     if (REDUCE) {
       bool bad;
       double rho = p.rho_ref + drho;
@@ -316,9 +352,10 @@ __global__ __launch_bounds__(256) void fused_kernel(StepParams p, const S* __res
       stencil_sums(pE, psn, pW, psm, pNE, pNW, pSW, pSE, Sx, Sy);
       NodeMacro mac = collide_node(p, dc, drc, jxc, jyc, psc, Sx, Sy);
       const size_t k = (size_t)y * p.nx + x;
-      const double c = ref_offset<S>(f, plane, k);
+      double cd[9];
+      dest_refs<S>(p, f, mask, x, y, cd);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) fo[(size_t)i * plane + k] = store_value<S>(dc[i], wgt(i), c);
+      for (int i = 0; i < 9; ++i) fo[(size_t)i * plane + k] = store_value<S>(dc[i], wgt(i), cd[i]);
       if (REDUCE) {
         acc[RED_WALLX] += wallc[0];
         acc[RED_WALLY] += wallc[1];
@@ -780,26 +817,22 @@ struct AMarch {
   bool hl;    // lane 0 or lane 63
   int y1;
   unsigned colB[9], colH[9];  // byte offsets of the pulled columns (interior strips)
-  // float storage: the reference plane, and the lane's column for the halo
-  // reference load (lane 0: x0-1, lane 1: x0-2, lane 62: x0+65, lane 63: x0+64)
+  // float storage: the reference plane
   __amdgpu_buffer_rsrc_t ref;
   unsigned refbytes;
-  ColGeo hc;
-  bool lane0;
 };
 
-// Reference offsets carried with pulled row q (float storage): c of rows
-// q-1, q, q+1 (j = 0, 1, 2) at the lane's column (cm) and at its halo
-// reference column (ch).
-struct RefRows {
-  float cm[3], ch[3];
+// Reference offsets of one row (float storage): c at the lane's column (m)
+// and, on lanes 0 and 63, at the column beside the strip (h).
+struct RefRow {
+  float m, h;
 };
 
 template <class S>
 struct ASlot {
   S raw[9];   // the lane's 9 pulled populations (stored values)
   S rawh[9];  // lanes 0 and 63: those of the halo column
-  RefRows r;  // float storage only
+  RefRow r;   // float storage: the reference offsets of this row
 };
 
 struct ARow {
@@ -807,6 +840,7 @@ struct ARow {
   double psih;  // psi of the halo column (lanes 0 and 63)
   bool bad;
   RowGeo g;
+  RefRow cr;  // float storage: the reference offsets of this row
 };
 
 template <class S, bool INTERIOR>
@@ -834,16 +868,11 @@ __device__ inline void aissue_row(const StepParams& p, const AMarch& m, int y, b
   load_row<S>(m.in, off, sl.raw);
   load_row<S>(m.in, offh, sl.rawh);
   if constexpr (sizeof(S) == 4) {
-    // rows q-1, q, q+1 (a row beyond a wall is only a bounce-back source,
-    // which takes the node's own offset; its value is not used)
-    const unsigned ro[3] = {g.bot, g.own, g.top};
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      unsigned om = (live && g.real) ? (ro[j] + m.c.own) * 4u : m.refbytes;
-      unsigned oh = (live && g.real && m.hc.real) ? (ro[j] + m.hc.own) * 4u : m.refbytes;
-      sl.r.cm[j] = BufIO<float>::load(m.ref, om);
-      sl.r.ch[j] = BufIO<float>::load(m.ref, oh);
-    }
+    // every population pulled into this row was stored relative to the
+    // puller's own offset: one offset per node
+    const bool rr = live && g.real;
+    sl.r.m = BufIO<float>::load(m.ref, rr ? (g.own + m.c.own) * 4u : m.refbytes);
+    sl.r.h = BufIO<float>::load(m.ref, (rr && m.h.real) ? (g.own + m.h.own) * 4u : m.refbytes);
   }
 }
 
@@ -855,52 +884,51 @@ __device__ inline float fbits_dpp(float v, float fill) {
                                                                __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
 }
 
-// Reference offsets of the 9 source nodes of row q's pulled populations: for
-// the lane (c) and, on lanes 0 and 63, for the halo column (chh).  The source
-// of direction i is x - e_i, or the node itself across a wall.
-__device__ inline void source_refs(const AMarch& m, const RowGeo& g, const RefRows& r, float c[9], float chh[9]) {
-  float cw[3], ce[3], h2[3];
+// Reference offsets of the nodes that pull row q's post-collision
+// populations, from the reference rows q-1 (`rb`), q (`r0`) and q+1 (`rt`):
+// cd[i] = c(x + e_i), or c(x) when x + e_i lies beyond a wall.  Lane 0's west
+// and lane 63's east neighbours are the columns beside the strip.
+template <bool INTERIOR>
+__device__ inline void dest_refs_row(const AMarch& m, const RowGeo& g, const RefRow& rb, const RefRow& r0,
+                                     const RefRow& rt, float cd[9]) {
+  const float cm[3] = {rb.m, r0.m, rt.m}, ch[3] = {rb.h, r0.h, rt.h};
+  float cw[3], ce[3];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    cw[j] = fbits_dpp<0x138>(r.cm[j], r.ch[j]);  // x - 1 (lane 0: its halo column x0-1)
-    ce[j] = fbits_dpp<0x130>(r.cm[j], r.ch[j]);  // x + 1 (lane 63: x0+64)
-    // lane 0 <- lane 1's halo load (x0-2), lane 63 <- lane 62's (x0+65)
-    h2[j] = fbits_dpp<0x138>(r.ch[j], fbits_dpp<0x130>(r.ch[j], r.ch[j]));
+    cw[j] = fbits_dpp<0x138>(cm[j], ch[j]);  // x - 1 (lane 0: column x0-1)
+    ce[j] = fbits_dpp<0x130>(cm[j], ch[j]);  // x + 1 (lane 63: column x0+64)
   }
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const int exi = ex(i), eyi = ey(i);
-    const int j = 1 - eyi;
-    const bool wall = (eyi == 1 && g.wall_b) || (eyi == -1 && g.wall_t) || (exi == 1 && m.c.wall_l) ||
-                      (exi == -1 && m.c.wall_r);
-    const float src = exi == 1 ? cw[j] : (exi == -1 ? ce[j] : r.cm[j]);
-    c[i] = wall ? r.cm[1] : src;
-    const bool wallh = (eyi == 1 && g.wall_b) || (eyi == -1 && g.wall_t) || (exi == 1 && m.h.wall_l) ||
-                       (exi == -1 && m.h.wall_r);
-    // halo column x0-1 (lane 0): sources x0-2, x0-1, x0; x0+64 (lane 63): x0+63, x0+64, x0+65
-    const bool far = (exi == 1) == m.lane0;
-    const float hs = exi == 0 ? r.ch[j] : (far ? h2[j] : r.cm[j]);
-    chh[i] = wallh ? r.ch[1] : hs;
+    const int j = 1 + eyi;
+    const float dst = exi == 1 ? ce[j] : (exi == -1 ? cw[j] : cm[j]);
+    if (INTERIOR) {
+      cd[i] = dst;
+    } else {
+      const bool wall = (eyi == 1 && g.wall_t) || (eyi == -1 && g.wall_b) || (exi == 1 && m.c.wall_r) ||
+                        (exi == -1 && m.c.wall_l);
+      cd[i] = wall ? r0.m : dst;
+    }
   }
 }
 
 template <class S>
 __device__ inline void arow_state(const StepParams& p, const AMarch& m, const ASlot<S>& sl, ARow& t) {
-  double d[9];
-  double h = 0.0;
+  double d[9], dh[9];
   if constexpr (sizeof(S) == 4) {
-    float c[9], chh[9];
-    source_refs(m, t.g, sl.r, c, chh);
+    const double cm = (double)sl.r.m, ch = (double)sl.r.h;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      d[i] = (double)sl.raw[i] + wgt(i) * (double)c[i];
-      h += (double)sl.rawh[i] + wgt(i) * (double)chh[i];
+      d[i] = (double)sl.raw[i] + wgt(i) * cm;
+      dh[i] = (double)sl.rawh[i] + wgt(i) * ch;
     }
+    t.cr = sl.r;
   } else {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       d[i] = (double)sl.raw[i];
-      h += (double)sl.rawh[i];
+      dh[i] = (double)sl.rawh[i];
     }
   }
   node_sums(d, t.drho, t.jx, t.jy);
@@ -908,8 +936,11 @@ __device__ inline void arow_state(const StepParams& p, const AMarch& m, const AS
   const double ps = psi_of(p, p.rho_ref + t.drho, bad);
   t.psi = t.g.real ? ps : p.psi_solid;
   t.bad = t.g.real && bad;
+  // the halo column's density in the same arithmetic as its own strip uses
+  double hr, hx, hy;
+  node_sums(dh, hr, hx, hy);
   bool badh;
-  const double psh = psi_of(p, p.rho_ref + h, badh);
+  const double psh = psi_of(p, p.rho_ref + hr, badh);
   t.psih = (t.g.real && m.h.real) ? psh : p.psi_solid;
 }
 
@@ -931,13 +962,10 @@ __device__ inline void amarch_row(const StepParams& p, const AMarch& m, int y, c
   const double pNW = wave_shr1_fill(t1.psi, t1.psih);
   const double pNE = wave_shl1_fill(t1.psi, t1.psih);
   double d[9];
-  double c_own = 0.0;
   if constexpr (sizeof(S) == 4) {
-    float c[9], chh[9];
-    source_refs(m, t0.g, s0.r, c, chh);
+    const double cm = (double)t0.cr.m;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) d[i] = (double)s0.raw[i] + wgt(i) * (double)c[i];
-    c_own = (double)s0.r.cm[1];
+    for (int i = 0; i < 9; ++i) d[i] = (double)s0.raw[i] + wgt(i) * cm;
   } else {
 #pragma unroll
     for (int i = 0; i < 9; ++i) d[i] = (double)s0.raw[i];
@@ -948,11 +976,18 @@ __device__ inline void amarch_row(const StepParams& p, const AMarch& m, int y, c
 #pragma unroll
   for (int i = 0; i < 9; ++i) dw[i] = d[i];
   NodeMacro mac = collide_node(p, d, t0.drho, t0.jx, t0.jy, t0.psi, Sx, Sy);
+  float cd[9];
+  if constexpr (sizeof(S) == 4) {
+    dest_refs_row<INTERIOR>(m, t0.g, tm.cr, t0.cr, t1.cr, cd);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) cd[i] = 0.0f;
+  }
   const bool store = t0.g.real;
   const unsigned k = t0.g.own + m.c.own;
 #pragma unroll
   for (int i = 0; i < 9; ++i)
-    BufIO<S>::store(store_value<S>(d[i], wgt(i), c_own), m.out,
+    BufIO<S>::store(store_value<S>(d[i], wgt(i), (double)cd[i]), m.out,
                     store ? ((unsigned)i * m.N + k) * (unsigned)sizeof(S) : m.bytes);
   if (REDUCE && store) {
     if (!INTERIOR) {
@@ -1067,7 +1102,6 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
   m.out = __builtin_amdgcn_make_buffer_rsrc((void*)fo, (short)0, (int)m.bytes, 0x00020000);
   const int x0 = strip * WAVE;
   m.hl = lane == 0 || lane == WAVE - 1;
-  m.lane0 = lane == 0;
   m.c = col_geo(p, x0 + lane, true);
   m.h = col_geo(p, lane == 0 ? x0 - 1 : x0 + WAVE, m.hl);
 #pragma unroll
@@ -1080,8 +1114,6 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
     // the reference plane follows the 9 population planes
     m.refbytes = m.N * 4u;
     m.ref = __builtin_amdgcn_make_buffer_rsrc((void*)(f + (size_t)9 * m.N), (short)0, (int)m.refbytes, 0x00020000);
-    const int xr = lane == 0 ? x0 - 1 : lane == 1 ? x0 - 2 : lane == WAVE - 2 ? x0 + WAVE + 1 : x0 + WAVE;
-    m.hc = col_geo(p, xr, lane <= 1 || lane >= WAVE - 2);
   }
   const int y0 = seg * seg_len;
   m.y1 = min(y0 + seg_len, p.ny);
@@ -1146,10 +1178,10 @@ void fused_shape(int nx, int ny, int seg_len, bool aligned, int* n_strips, int* 
 }
 
 template <class S>
-hipError_t launch_init(const StepParams& p, const double* rho0, const double* ux0, const double* uy0, void* fa,
-                       void* fb, hipStream_t st) {
+hipError_t launch_init(const StepParams& p, const double* rho0, const double* ux0, const double* uy0,
+                       const uint8_t* mask, void* fa, void* fb, hipStream_t st) {
   dim3 blk(64, 4);
-  hipLaunchKernelGGL(init_kernel<S>, node_grid(p, blk), blk, 0, st, p, rho0, ux0, uy0, (S*)fa, (S*)fb);
+  hipLaunchKernelGGL(init_kernel<S>, node_grid(p, blk), blk, 0, st, p, rho0, ux0, uy0, mask, (S*)fa, (S*)fb);
   return hipGetLastError();
 }
 
@@ -1223,7 +1255,13 @@ hipError_t launch_step(const StepParams& p, const StepLaunch& L, hipStream_t st)
 
 hipError_t launch_reref(const StepParams& p, void* fa, void* fb, const uint8_t* mask, hipStream_t st) {
   dim3 blk(64, 4);
-  hipLaunchKernelGGL(reref_kernel, node_grid(p, blk), blk, 0, st, p, (float*)fa, (float*)fb, mask);
+  hipLaunchKernelGGL(reref_new_kernel, node_grid(p, blk), blk, 0, st, p, (const float*)fa, (float*)fb, mask);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(reref_shift_kernel, node_grid(p, blk), blk, 0, st, p, (float*)fa, (float*)fb, mask);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(reref_copy_kernel, node_grid(p, blk), blk, 0, st, p, (float*)fa, (const float*)fb);
   return hipGetLastError();
 }
 
@@ -1244,10 +1282,10 @@ hipError_t launch_finalize(const double* partials, int n_parts, double* out, hip
   return hipGetLastError();
 }
 
-template hipError_t launch_init<float>(const StepParams&, const double*, const double*, const double*, void*, void*,
-                                       hipStream_t);
-template hipError_t launch_init<double>(const StepParams&, const double*, const double*, const double*, void*, void*,
-                                        hipStream_t);
+template hipError_t launch_init<float>(const StepParams&, const double*, const double*, const double*,
+                                       const uint8_t*, void*, void*, hipStream_t);
+template hipError_t launch_init<double>(const StepParams&, const double*, const double*, const double*,
+                                        const uint8_t*, void*, void*, hipStream_t);
 template hipError_t launch_step<float>(const StepParams&, const StepLaunch&, hipStream_t);
 template hipError_t launch_step<double>(const StepParams&, const StepLaunch&, hipStream_t);
 template hipError_t launch_fields<float>(const StepParams&, const void*, const uint8_t*, const double*, void*, double*,

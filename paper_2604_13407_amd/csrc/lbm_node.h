@@ -5,13 +5,17 @@
 // M (w_i R) = R (1, -2, 1, 0, 0, 0, 0, 0, 0), the collision acts on deviation
 // moments with m^eq shifted by the same vector; all other terms are unchanged.
 //
-// Storage convention: double storage keeps d_i.  Float storage keeps
-// s_i(x) = f_i(x) - w_i rhat(x) = d_i(x) - w_i c(x) with a per-node reference
-// density rhat(x) = R + c(x), the offset c held as a tenth float plane of the
-// population array (the initial density, unless re-referenced).  Deviations
-// from the node's own reference stay small in liquid and vapour alike, so the
-// one rounding per stored population is small wherever the density has not
-// moved far from the reference.
+// Storage convention: double storage keeps d_i.  Float storage keeps each
+// post-collision population relative to the reference density of the node
+// that will pull it: s_i(x) = fbar_i(x) - w_i rhat(x + e_i), or - w_i rhat(x)
+// when x + e_i is solid or beyond a wall (the population then returns to x by
+// bounce-back).  The per-node reference density rhat = R + c has its offset c
+// held as a tenth float plane of the population array (the initial density,
+// unless re-referenced).  A pull at x therefore adds the same w_i c(x) to
+// every population it gathers, and the store at x subtracts the offsets of
+// its 8 neighbours.  The stored values stay small in liquid and vapour alike
+// (at an interface they are of the order of the density step between two
+// neighbours), so the one rounding per stored population is small.
 //
 // Arithmetic is double for both storage types: loads are widened, the step is
 // computed in double and each population is rounded once when stored.  In
@@ -135,13 +139,37 @@ __host__ __device__ inline double ref_offset(const S* __restrict__ f, size_t pla
   }
 }
 
-// Stored value of a post-collision deviation d at a node with offset c.
+// Stored value of a post-collision deviation d whose puller has offset c.
 template <class S>
 __host__ __device__ inline S store_value(double d, double w, double c) {
   if constexpr (sizeof(S) == 4) {
     return (S)(d - w * c);
   } else {
     return (S)d;
+  }
+}
+
+// Reference offsets (float storage) of the nodes that pull node (x, y)'s
+// post-collision populations: c[i] = c(x + e_i), or c(x) when x + e_i is solid
+// or beyond a wall.  Zero for double storage.
+template <class S>
+__host__ __device__ inline void dest_refs(const StepParams& p, const S* __restrict__ f, const uint8_t* __restrict__ mask,
+                                          int x, int y, double c[9]) {
+  if constexpr (sizeof(S) == 4) {
+    const size_t plane = (size_t)p.nx * p.ny;
+    const size_t self = (size_t)y * p.nx + x;
+    const double c_self = ref_offset<S>(f, plane, self);
+    c[0] = c_self;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      int xd, yd;
+      bool inside;
+      const bool sol = solid_at(p, mask, x + ex(i), y + ey(i), xd, yd, inside);
+      c[i] = sol ? c_self : ref_offset<S>(f, plane, (size_t)yd * p.nx + xd);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) c[i] = 0.0;
   }
 }
 
@@ -153,6 +181,7 @@ __host__ __device__ inline void pull_node(const StepParams& p, const S* __restri
                                           const double* __restrict__ wall_u, int x, int y, double d[9], double* wall) {
   const size_t plane = (size_t)p.nx * p.ny;
   const size_t self = (size_t)y * p.nx + x;
+  // every population gathered here was stored relative to this node's offset
   const double c_self = ref_offset<S>(f, plane, self);
   d[0] = (double)f[self] + wgt(0) * c_self;
   double rho_w = 0.0;
@@ -164,17 +193,19 @@ __host__ __device__ inline void pull_node(const StepParams& p, const S* __restri
     bool sol = solid_at(p, mask, x - ex(i), y - ey(i), xs, ys, inside);
     if (!sol) {
       const size_t ks = (size_t)ys * p.nx + xs;
-      d[i] = (double)f[(size_t)i * plane + ks] + wgt(i) * ref_offset<S>(f, plane, ks);
+      d[i] = (double)f[(size_t)i * plane + ks] + wgt(i) * c_self;
     } else {
       double v = (double)f[(size_t)opp(i) * plane + self] + wgt(i) * c_self;
       double mw = 0.0;
       if (wall_u && inside) {
         if (!have_rho_w) {
           // density of this node at the previous step: sum of its own fbar
+          double cd[9];
+          dest_refs<S>(p, f, mask, x, y, cd);
           double s = 0.0;
 #pragma unroll
-          for (int q = 0; q < 9; ++q) s += (double)f[(size_t)q * plane + self];
-          rho_w = p.rho_ref + c_self + s;
+          for (int q = 0; q < 9; ++q) s += (double)f[(size_t)q * plane + self] + wgt(q) * cd[q];
+          rho_w = p.rho_ref + s;
           have_rho_w = true;
         }
         size_t ks = (size_t)ys * p.nx + xs;

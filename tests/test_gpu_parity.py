@@ -231,20 +231,16 @@ def test_runs_are_deterministic():
     assert outs[0][1] == outs[1][1]
 
 
-@pytest.mark.parametrize("nx,ny,px,py,use_mask", [
-    (1, 1, True, True, True), (2, 3, True, True, True), (63, 17, False, False, True), (64, 5, True, False, True),
-    (125, 9, False, True, True), (200, 1, True, True, True),
-    # without a mask these take the aligned 64-column kernel
-    (64, 5, True, False, False), (128, 1, True, True, False), (64, 2, False, True, False),
-    (192, 7, False, False, False)])
-def test_edge_shapes_fp64(nx, ny, px, py, use_mask):
+def edge_case_run(nx, ny, px, py, use_mask, precision, steps=7):
+    """A random-density lattice of an edge shape, stepped on the GPU and in the oracle."""
+    print(f"[edge] {nx}x{ny} px={px} py={py} mask={use_mask} precision={precision}", flush=True)
     rng = np.random.default_rng(nx * 100 + ny)
     w = WL.small_droplet()
     w = w.with_size(nx, ny, periodic_x=px, periodic_y=py, init="none", perturb=0.05, seed=nx + ny)
     mask = None
     if use_mask and nx * ny > 50:
         mask = (rng.random((ny, nx)) < 0.1).astype(np.uint8)
-    lat = LT.Lattice(nx, ny, px, py, LT.FP64, LT.KERNEL_FUSED, mask=mask)
+    lat = LT.Lattice(nx, ny, px, py, precision, LT.KERNEL_FUSED, mask=mask)
     lat.set_eos(w.eos_kind, w.a, w.b, w.R, w.T, w.k_eos)
     lat.set_relaxation(w.s)
     lat.set_scheme(w.scheme, w.eps)
@@ -254,20 +250,49 @@ def test_edge_shapes_fp64(nx, ny, px, py, use_mask):
     rho0 = 0.05 + 0.2 * rng.random((ny, nx))
     lat.init_equilibrium(rho0)
     lat.step(0)
-    lat.step(7)
+    lat.step(steps)
     g = gpu_fields(lat)
     p = O.Params(nx=nx, ny=ny, periodic_x=px, periodic_y=py, eos_kind=w.eos_kind, T=w.T, eps=w.eps, s=w.s,
                  scheme=w.scheme, force_mode=O.FORCE_BUOYANT, fx=1e-6, fy=-2e-6, rho_g=w.rho_g, rho_l=w.rho_l,
                  rho_s=w.rho_s)
     o = O.Oracle(p, mask=mask).init(rho0)
-    o.step(7)
-    om = o.macros()
+    o.step(steps)
     fl = np.ones((ny, nx), bool) if mask is None else mask == 0
+    return g, o.macros(), fl
+
+
+EDGE_SHAPES = [
+    (1, 1, True, True, True), (2, 3, True, True, True), (63, 17, False, False, True), (64, 5, True, False, True),
+    (125, 9, False, True, True), (200, 1, True, True, True),
+    # without a mask these take the aligned 64-column kernel
+    (64, 5, True, False, False), (128, 1, True, True, False), (64, 2, False, True, False),
+    (192, 7, False, False, False)]
+
+
+@pytest.mark.parametrize("nx,ny,px,py,use_mask", EDGE_SHAPES)
+def test_edge_shapes_fp64(nx, ny, px, py, use_mask):
+    g, om, fl = edge_case_run(nx, ny, px, py, use_mask, LT.FP64)
     psi_max = np.max(np.abs(om["psi"]))
     for k in FIELDS:
         scale = field_scale(k, om[k][fl], psi_max) if fl.any() else 1.0
         err = np.max(np.abs(g[k][fl] - om[k][fl])) / scale if fl.any() else 0.0
         assert err <= 1e-12, (k, err)
+
+
+@pytest.mark.parametrize("nx,ny,px,py,use_mask", EDGE_SHAPES + [
+    (64, 1, True, True, False), (64, 3, True, True, False), (256, 2, True, True, False), (64, 4, False, False, False)])
+def test_edge_shapes_fp32(nx, ny, px, py, use_mask):
+    """Float storage with its per-node reference plane: rows and columns that wrap onto
+    themselves (one or two rows, one strip) take their reference offsets from the right
+    nodes."""
+    g, om, fl = edge_case_run(nx, ny, px, py, use_mask, LT.FP32_DEV)
+    if not fl.any():
+        return
+    rerr = np.max(np.abs(g["rho"][fl] - om["rho"][fl]) / om["rho"][fl])
+    umax = max(np.max(np.abs(om["ux"][fl])), np.max(np.abs(om["uy"][fl])))
+    uerr = max(np.max(np.abs(g["ux"][fl] - om["ux"][fl])), np.max(np.abs(g["uy"][fl] - om["uy"][fl]))) / umax
+    assert rerr <= 1e-5, ("rho", rerr)
+    assert uerr <= 1e-4, ("u", uerr)
 
 
 @pytest.mark.parametrize("make", [droplet_small, droplet_aligned])
