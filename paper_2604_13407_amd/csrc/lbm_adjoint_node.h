@@ -256,9 +256,9 @@ __host__ __device__ inline void adj_traj_node(const StepParams& p, const S* __re
   const size_t k = (size_t)y * p.nx + x;
   double dr = 0.0, jx = 0.0, jy = 0.0, ps = p.psi_solid;
   if (!(mask && mask[k])) {
-    double d[9];
-    pull_node<S>(p, f, mask, nullptr, x, y, d, nullptr);
-    node_sums(d, dr, jx, jy);
+    double d[9], c;
+    pull_node<S>(p, f, mask, nullptr, x, y, d, nullptr, c);
+    node_sums<S>(d, c, dr, jx, jy);
     bool bad;
     ps = psi_of(p, p.rho_ref + dr, bad);
   }

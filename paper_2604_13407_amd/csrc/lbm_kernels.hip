@@ -143,10 +143,10 @@ __global__ void psi_kernel(StepParams p, const S* __restrict__ f, const uint8_t*
     psi_out[k] = p.psi_solid;
     return;
   }
-  double d[9];
-  pull_node<S>(p, f, mask, wall_u, x, y, d, nullptr);
+  double d[9], c;
+  pull_node<S>(p, f, mask, wall_u, x, y, d, nullptr, c);
   double drho, jx, jy;
-  node_sums(d, drho, jx, jy);
+  node_sums<S>(d, c, drho, jx, jy);
   bool bad;
   psi_out[k] = psi_of(p, p.rho_ref + drho, bad);
 }
@@ -196,14 +196,15 @@ __global__ void collide_kernel(StepParams p, const S* __restrict__ f, S* __restr
   if (active && !(mask && mask[k])) {
     double d[9];
     double wall[2] = {0.0, 0.0};
-    pull_node<S>(p, f, mask, wall_u, x, y, d, REDUCE ? wall : nullptr);
+    double c;
+    pull_node<S>(p, f, mask, wall_u, x, y, d, REDUCE ? wall : nullptr, c);
     double drho, jx, jy;
-    node_sums(d, drho, jx, jy);
+    node_sums<S>(d, c, drho, jx, jy);
     double Sx, Sy;
     stencil_sums(psi_at(p, psi, mask, x + 1, y), psi_at(p, psi, mask, x, y + 1), psi_at(p, psi, mask, x - 1, y),
                  psi_at(p, psi, mask, x, y - 1), psi_at(p, psi, mask, x + 1, y + 1), psi_at(p, psi, mask, x - 1, y + 1),
                  psi_at(p, psi, mask, x - 1, y - 1), psi_at(p, psi, mask, x + 1, y - 1), Sx, Sy);
-    NodeMacro mac = collide_node(p, d, drho, jx, jy, psi[k], Sx, Sy);
+    NodeMacro mac = collide_node<S>(p, d, c, drho, jx, jy, psi[k], Sx, Sy);
     const size_t plane = (size_t)p.nx * p.ny;
     double cd[9];
     dest_refs<S>(p, f, mask, x, y, cd);
@@ -240,16 +241,17 @@ __global__ void fields_kernel(StepParams p, const S* __restrict__ f, const uint8
     if (!(mask && mask[k])) {
       double d[9];
       double wall[2] = {0.0, 0.0};
-      pull_node<S>(p, f, mask, wall_u, x, y, d, reduce ? wall : nullptr);
+      double c;
+      pull_node<S>(p, f, mask, wall_u, x, y, d, reduce ? wall : nullptr, c);
       double drho, jx, jy;
-      node_sums(d, drho, jx, jy);
+      node_sums<S>(d, c, drho, jx, jy);
       r = p.rho_ref + drho;
       double Sx, Sy;
       stencil_sums(psi_at(p, psi, mask, x + 1, y), psi_at(p, psi, mask, x, y + 1), psi_at(p, psi, mask, x - 1, y),
                    psi_at(p, psi, mask, x, y - 1), psi_at(p, psi, mask, x + 1, y + 1),
                    psi_at(p, psi, mask, x - 1, y + 1), psi_at(p, psi, mask, x - 1, y - 1),
                    psi_at(p, psi, mask, x + 1, y - 1), Sx, Sy);
-      NodeMacro mac = collide_node(p, d, drho, jx, jy, ps, Sx, Sy);
+      NodeMacro mac = collide_node<S>(p, d, c, drho, jx, jy, ps, Sx, Sy);
       u = mac.ux;
       v = mac.uy;
       fxi = -p.G * ps * Sx;
@@ -282,8 +284,8 @@ __global__ void fields_kernel(StepParams p, const S* __restrict__ f, const uint8
 template <class S>
 __device__ inline void strip_row_pull(const StepParams& p, const S* __restrict__ f, const uint8_t* __restrict__ mask,
                                       const double* __restrict__ wall_u, int x, int y, bool lane_in, double d[9],
-                                      double& drho, double& jx, double& jy, double& psi, bool& fluid, bool& bad,
-                                      double* wall) {
+                                      double& c, double& drho, double& jx, double& jy, double& psi, bool& fluid,
+                                      bool& bad, double* wall) {
   // classify (x, y): outside the box across a wall, masked solid, or fluid
   int xw = 0, yw = 0;
   bool inside;
@@ -291,12 +293,12 @@ __device__ inline void strip_row_pull(const StepParams& p, const S* __restrict__
   fluid = !sol;
   bad = false;
   if (fluid) {
-    pull_node<S>(p, f, mask, wall_u, xw, yw, d, wall);
-    node_sums(d, drho, jx, jy);
+    pull_node<S>(p, f, mask, wall_u, xw, yw, d, wall, c);
+    node_sums<S>(d, c, drho, jx, jy);
     psi = psi_of(p, p.rho_ref + drho, bad);
   } else {
     psi = p.psi_solid;
-    drho = jx = jy = 0.0;
+    c = drho = jx = jy = 0.0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) d[i] = 0.0;
   }
@@ -326,6 +328,7 @@ __global__ __launch_bounds__(256) void fused_kernel(StepParams p, const S* __res
   for (int q = 0; q < RED_COUNT; ++q) acc[q] = 0.0;
 
   double dc[9], dn[9];
+  double cc, cn;
   double drc, jxc, jyc, drn, jxn, jyn;
   double psm, psc, psn;
   bool flc, fln, badc, badn;
@@ -333,15 +336,16 @@ __global__ __launch_bounds__(256) void fused_kernel(StepParams p, const S* __res
 
   // prologue: halo row y0-1 (psi only) and row y0
   {
-    double dtmp[9], a, b, c;
+    double dtmp[9], ct, a, b, c;
     bool ftmp, btmp;
-    strip_row_pull<S>(p, f, mask, wall_u, x, y0 - 1, lane_in, dtmp, a, b, c, psm, ftmp, btmp, nullptr);
+    strip_row_pull<S>(p, f, mask, wall_u, x, y0 - 1, lane_in, dtmp, ct, a, b, c, psm, ftmp, btmp, nullptr);
   }
-  strip_row_pull<S>(p, f, mask, wall_u, x, y0, lane_in, dc, drc, jxc, jyc, psc, flc, badc, REDUCE ? wallc : nullptr);
+  strip_row_pull<S>(p, f, mask, wall_u, x, y0, lane_in, dc, cc, drc, jxc, jyc, psc, flc, badc,
+                    REDUCE ? wallc : nullptr);
 
   for (int y = y0; y < y1; ++y) {
     walln[0] = walln[1] = 0.0;
-    strip_row_pull<S>(p, f, mask, wall_u, x, y + 1, lane_in, dn, drn, jxn, jyn, psn, fln, badn,
+    strip_row_pull<S>(p, f, mask, wall_u, x, y + 1, lane_in, dn, cn, drn, jxn, jyn, psn, fln, badn,
                       (REDUCE && y + 1 < y1) ? walln : nullptr);
     // neighbours' psi through the wavefront (lanes 0 and 63 never collide)
     double pW = shfl_up1(psc), pE = shfl_down1(psc);
@@ -350,7 +354,7 @@ __global__ __launch_bounds__(256) void fused_kernel(StepParams p, const S* __res
     if (owner && flc) {
       double Sx, Sy;
       stencil_sums(pE, psn, pW, psm, pNE, pNW, pSW, pSE, Sx, Sy);
-      NodeMacro mac = collide_node(p, dc, drc, jxc, jyc, psc, Sx, Sy);
+      NodeMacro mac = collide_node<S>(p, dc, cc, drc, jxc, jyc, psc, Sx, Sy);
       const size_t k = (size_t)y * p.nx + x;
       double cd[9];
       dest_refs<S>(p, f, mask, x, y, cd);
@@ -367,6 +371,7 @@ __global__ __launch_bounds__(256) void fused_kernel(StepParams p, const S* __res
     psc = psn;
 #pragma unroll
     for (int i = 0; i < 9; ++i) dc[i] = dn[i];
+    cc = cn;
     drc = drn;
     jxc = jxn;
     jyc = jyn;
@@ -538,7 +543,7 @@ __device__ inline void row_state(const StepParams& p, const S raw[9], bool exist
   double d[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) d[i] = (double)raw[i];
-  node_sums(d, t.drho, t.jx, t.jy);
+  node_sums<S>(d, 0.0, t.drho, t.jx, t.jy);
   bool bad;
   double ps = psi_of(p, p.rho_ref + t.drho, bad);
   t.psi = exists ? ps : p.psi_solid;
@@ -604,7 +609,7 @@ __device__ inline void march_row(const StepParams& p, const March& m, int y, con
   for (int i = 0; i < 9; ++i) d[i] = (double)cur0[i];
   double Sx, Sy;
   stencil_sums(pE, t1.psi, pW, tm.psi, pNE, pNW, pSW, pSE, Sx, Sy);
-  NodeMacro mac = collide_node(p, d, t0.drho, t0.jx, t0.jy, t0.psi, Sx, Sy);
+  NodeMacro mac = collide_node<S>(p, d, 0.0, t0.drho, t0.jx, t0.jy, t0.psi, Sx, Sy);
   const bool store = m.owner && t0.g.real;
   const unsigned k = t0.g.own + m.c.own;
 #pragma unroll
@@ -648,7 +653,7 @@ __device__ inline void march_row4(const StepParams& p, const March& m, int y, co
   for (int i = 0; i < 9; ++i) d[i] = (double)cur0[i];
   double Sx, Sy;
   stencil_sums(pE, t1.psi, pW, tm.psi, pNE, pNW, pSW, pSE, Sx, Sy);
-  NodeMacro mac = collide_node(p, d, t0.drho, t0.jx, t0.jy, t0.psi, Sx, Sy);
+  NodeMacro mac = collide_node<S>(p, d, 0.0, t0.drho, t0.jx, t0.jy, t0.psi, Sx, Sy);
   const bool store = m.owner && t0.g.real;
   const unsigned k = t0.g.own + m.c.own;
 #pragma unroll
@@ -916,29 +921,25 @@ __device__ inline void dest_refs_row(const AMarch& m, const RowGeo& g, const Ref
 template <class S>
 __device__ inline void arow_state(const StepParams& p, const AMarch& m, const ASlot<S>& sl, ARow& t) {
   double d[9], dh[9];
-  if constexpr (sizeof(S) == 4) {
-    const double cm = (double)sl.r.m, ch = (double)sl.r.h;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      d[i] = (double)sl.raw[i] + wgt(i) * cm;
-      dh[i] = (double)sl.rawh[i] + wgt(i) * ch;
-    }
-    t.cr = sl.r;
-  } else {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      d[i] = (double)sl.raw[i];
-      dh[i] = (double)sl.rawh[i];
-    }
+  for (int i = 0; i < 9; ++i) {
+    d[i] = (double)sl.raw[i];
+    dh[i] = (double)sl.rawh[i];
   }
-  node_sums(d, t.drho, t.jx, t.jy);
+  double cm = 0.0, ch = 0.0;
+  if constexpr (sizeof(S) == 4) {
+    cm = (double)sl.r.m;
+    ch = (double)sl.r.h;
+    t.cr = sl.r;
+  }
+  node_sums<S>(d, cm, t.drho, t.jx, t.jy);
   bool bad;
   const double ps = psi_of(p, p.rho_ref + t.drho, bad);
   t.psi = t.g.real ? ps : p.psi_solid;
   t.bad = t.g.real && bad;
   // the halo column's density in the same arithmetic as its own strip uses
   double hr, hx, hy;
-  node_sums(dh, hr, hx, hy);
+  node_sums<S>(dh, ch, hr, hx, hy);
   bool badh;
   const double psh = psi_of(p, p.rho_ref + hr, badh);
   t.psih = (t.g.real && m.h.real) ? psh : p.psi_solid;
@@ -962,20 +963,16 @@ __device__ inline void amarch_row(const StepParams& p, const AMarch& m, int y, c
   const double pNW = wave_shr1_fill(t1.psi, t1.psih);
   const double pNE = wave_shl1_fill(t1.psi, t1.psih);
   double d[9];
-  if constexpr (sizeof(S) == 4) {
-    const double cm = (double)t0.cr.m;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) d[i] = (double)s0.raw[i] + wgt(i) * cm;
-  } else {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) d[i] = (double)s0.raw[i];
-  }
+  for (int i = 0; i < 9; ++i) d[i] = (double)s0.raw[i];
+  double cm = 0.0;
+  if constexpr (sizeof(S) == 4) cm = (double)t0.cr.m;
   double Sx, Sy;
   stencil_sums(pE, t1.psi, pW, tm.psi, pNE, pNW, pSW, pSE, Sx, Sy);
   double dw[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) dw[i] = d[i];
-  NodeMacro mac = collide_node(p, d, t0.drho, t0.jx, t0.jy, t0.psi, Sx, Sy);
+  NodeMacro mac = collide_node<S>(p, d, cm, t0.drho, t0.jx, t0.jy, t0.psi, Sx, Sy);
   float cd[9];
   if constexpr (sizeof(S) == 4) {
     dest_refs_row<INTERIOR>(m, t0.g, tm.cr, t0.cr, t1.cr, cd);
@@ -999,7 +996,7 @@ __device__ inline void amarch_row(const StepParams& p, const AMarch& m, int y, c
                           (exi == -1 && m.c.wall_r);
         if (wall) {
           // the pulled deviation at a wall link is the node's own opposite population
-          double both = 2.0 * (dw[i] + wgt(i) * p.rho_ref);
+          double both = 2.0 * (dw[i] + wgt(i) * (p.rho_ref + cm));
           wx -= exi * both;
           wy -= eyi * both;
         }

@@ -4,6 +4,9 @@
 // a uniform R (rho_ref; 0 for double storage, so d_i = f_i).  Since
 // M (w_i R) = R (1, -2, 1, 0, 0, 0, 0, 0, 0), the collision acts on deviation
 // moments with m^eq shifted by the same vector; all other terms are unchanged.
+// Float storage pulls deviations from a per-node density R + c instead; the
+// same identity moves their moments to the uniform R (rho + c, e - 2c,
+// eps + c), and the collision's output is again relative to R.
 //
 // Storage convention: double storage keeps d_i.  Float storage keeps each
 // post-collision population relative to the reference density of the node
@@ -174,16 +177,20 @@ __host__ __device__ inline void dest_refs(const StepParams& p, const S* __restri
 }
 
 // Pull streaming (Eq. 2b) with halfway bounce-back: d[i] = dbar_i(x - e_i), or
-// dbar_opp(i)(x) (+ the moving-wall term) when x - e_i is solid.  When
-// `wall` is non-null, accumulates the momentum handed to the walls.
+// dbar_opp(i)(x) (+ the moving-wall term) when x - e_i is solid, as
+// deviations from w_i (R + c) with c the node's reference offset (returned;
+// 0 for double storage).  When `wall` is non-null, accumulates the momentum
+// handed to the walls.
 template <class S>
 __host__ __device__ inline void pull_node(const StepParams& p, const S* __restrict__ f, const uint8_t* __restrict__ mask,
-                                          const double* __restrict__ wall_u, int x, int y, double d[9], double* wall) {
+                                          const double* __restrict__ wall_u, int x, int y, double d[9], double* wall,
+                                          double& c) {
   const size_t plane = (size_t)p.nx * p.ny;
   const size_t self = (size_t)y * p.nx + x;
   // every population gathered here was stored relative to this node's offset
   const double c_self = ref_offset<S>(f, plane, self);
-  d[0] = (double)f[self] + wgt(0) * c_self;
+  c = c_self;
+  d[0] = (double)f[self];
   double rho_w = 0.0;
   bool have_rho_w = false;
 #pragma unroll
@@ -193,9 +200,9 @@ __host__ __device__ inline void pull_node(const StepParams& p, const S* __restri
     bool sol = solid_at(p, mask, x - ex(i), y - ey(i), xs, ys, inside);
     if (!sol) {
       const size_t ks = (size_t)ys * p.nx + xs;
-      d[i] = (double)f[(size_t)i * plane + ks] + wgt(i) * c_self;
+      d[i] = (double)f[(size_t)i * plane + ks];
     } else {
-      double v = (double)f[(size_t)opp(i) * plane + self] + wgt(i) * c_self;
+      double v = (double)f[(size_t)opp(i) * plane + self];
       double mw = 0.0;
       if (wall_u && inside) {
         if (!have_rho_w) {
@@ -216,7 +223,7 @@ __host__ __device__ inline void pull_node(const StepParams& p, const S* __restri
       d[i] = v;
       if (wall) {
         // the wall received -(f_i + fbar_opp) e_i, with f_i = fbar_opp + mw
-        double fi = v + wgt(i) * p.rho_ref;
+        double fi = v + wgt(i) * (p.rho_ref + c_self);
         double both = 2.0 * fi - mw;
         wall[0] -= ex(i) * both;
         wall[1] -= ey(i) * both;
@@ -225,9 +232,10 @@ __host__ __device__ inline void pull_node(const StepParams& p, const S* __restri
   }
 }
 
-// Density deviation and lattice momentum of the pulled populations, in a fixed
-// summation order.
-__host__ __device__ inline void node_sums(const double d[9], double& drho, double& jx, double& jy) {
+// Density deviation (from R) and lattice momentum of pulled deviations d
+// relative to R + c, in a fixed summation order.
+template <class S>
+__host__ __device__ inline void node_sums(const double d[9], double c, double& drho, double& jx, double& jy) {
   double s13 = d[1] - d[3];
   double s24 = d[2] - d[4];
   double c57 = d[5] - d[7];
@@ -235,6 +243,7 @@ __host__ __device__ inline void node_sums(const double d[9], double& drho, doubl
   jx = s13 + (c57 + c86);
   jy = s24 + (c57 - c86);
   drho = d[0] + ((d[1] + d[3]) + (d[2] + d[4])) + ((d[5] + d[7]) + (d[6] + d[8]));
+  if constexpr (sizeof(S) == 4) drho += c;
 }
 
 // Stencil sums S = sum_k w_k psi(x + e_k) e_k of Eq. (4) (w = 1/3, 1/12),
@@ -252,15 +261,17 @@ struct NodeMacro {
 
 // Collision in moment space (Eq. 2a) with Eqs. (6)-(8), the force of Eq. (4)
 // and the source term of Eq. (11) or Eqs. (13) + (42).  d holds the pulled
-// deviations on entry and the post-collision deviations on exit.
-//   drho  : sum of the deviations (rho = rho_ref + drho), jx, jy : momentum
+// deviations on entry (from R + c; float storage only, c = 0 otherwise) and
+// the post-collision deviations from R on exit.
+//   drho  : rho - rho_ref, jx, jy : momentum
 //   psi_c : psi of this node, Sx, Sy : stencil sums of its neighbours
 // Q_m uses P_ab = F_a F_b / (G psi^2) = G S_a S_b, which is the same quantity
 // without the division (F_int = -G psi S).
 // Returns u (Eq. 3) and the total force.  The caller rounds d to the storage
 // type once per population.
-__host__ __device__ inline NodeMacro collide_node(const StepParams& p, double d[9], double drho, double jx, double jy,
-                                                  double psi_c, double Sx, double Sy) {
+template <class S>
+__host__ __device__ inline NodeMacro collide_node(const StepParams& p, double d[9], double c, double drho, double jx,
+                                                  double jy, double psi_c, double Sx, double Sy) {
   NodeMacro out;
   const double G = p.G;
   const double Fix = -G * psi_c * Sx;
@@ -287,8 +298,13 @@ __host__ __device__ inline NodeMacro collide_node(const StepParams& p, double d[
   const double s24 = d[2] - d[4];
   const double c57 = d[5] - d[7];
   const double c86 = d[8] - d[6];
-  const double m1 = 2.0 * s8 - s4 - 4.0 * d0;
-  const double m2 = 4.0 * d0 - 2.0 * s4 + s8;
+  double m1 = 2.0 * s8 - s4 - 4.0 * d0;
+  double m2 = 4.0 * d0 - 2.0 * s4 + s8;
+  if constexpr (sizeof(S) == 4) {
+    // from the node's reference R + c to R: M (w_i c) = c (1, -2, 1, 0, ...)
+    m1 -= 2.0 * c;
+    m2 += c;
+  }
   const double m4 = (c57 + c86) - 2.0 * s13;
   const double m6 = (c57 - c86) - 2.0 * s24;
   const double m7 = (d[1] + d[3]) - (d[2] + d[4]);
