@@ -411,23 +411,30 @@ template <class S>
 struct BufIO;
 template <>
 struct BufIO<float> {
-  static __device__ inline float load(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0));
+  // byte offset = per-lane `byte_off` + wavefront-uniform `soff`
+  static __device__ inline float load(__amdgpu_buffer_rsrc_t r, unsigned byte_off, unsigned soff = 0) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, (int)soff, 0));
   }
-  static __device__ inline void store(float v, __amdgpu_buffer_rsrc_t r, unsigned byte_off) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)byte_off, 0, 0);
+  static __device__ inline void store(float v, __amdgpu_buffer_rsrc_t r, unsigned byte_off, unsigned soff = 0) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)byte_off, (int)soff, 0);
   }
 };
 template <>
 struct BufIO<double> {
   typedef unsigned int u2 __attribute__((ext_vector_type(2)));
-  static __device__ inline double load(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0));
+  static __device__ inline double load(__amdgpu_buffer_rsrc_t r, unsigned byte_off, unsigned soff = 0) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, (int)soff, 0));
   }
-  static __device__ inline void store(double v, __amdgpu_buffer_rsrc_t r, unsigned byte_off) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)byte_off, 0, 0);
+  static __device__ inline void store(double v, __amdgpu_buffer_rsrc_t r, unsigned byte_off, unsigned soff = 0) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)byte_off, (int)soff, 0);
   }
 };
+
+// A buffer resource over `bytes` bytes at `base`; 0 bytes makes every access
+// out of range (loads return 0, stores are dropped).
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)bytes, 0x00020000);
+}
 
 // Lane l receives lane l-1's value (lane 0 keeps its own): DPP wave_shr:1.
 __device__ inline double wave_shr1(double v) {
@@ -814,17 +821,23 @@ __global__ __launch_bounds__(256) void fast_kernel(StepParams p, const S* __rest
 // lane 0 pulls column x0-1 and lane 63 column x0+64; the other lanes' offsets
 // are out of range, so those loads return 0 without a memory access.
 
+// Loads and stores take their row part as a wavefront-uniform offset and
+// their column part per lane; a row that is not loaded or not stored uses an
+// empty buffer resource instead of per-lane out-of-range offsets.  On lanes
+// other than 0 and 63 the halo loads read the lane's own pulled populations
+// again (the same cache lines as the row's main loads); their results are
+// not used.
 struct AMarch {
-  __amdgpu_buffer_rsrc_t in, out;
+  const void* f;
+  void* fo;
   unsigned N, bytes;
   ColGeo c;   // the lane's column
   ColGeo h;   // lane 0: column x0-1, lane 63: column x0+64; real where that node exists
-  bool hl;    // lane 0 or lane 63
   int y1;
   unsigned colB[9], colH[9];  // byte offsets of the pulled columns (interior strips)
-  // float storage: the reference plane
-  __amdgpu_buffer_rsrc_t ref;
-  unsigned refbytes;
+  // float storage: the reference plane, and the column byte offset of the
+  // halo column's reference (the lane's own where there is none)
+  unsigned refbytes, href;
 };
 
 // Reference offsets of one row (float storage): c at the lane's column (m)
@@ -851,33 +864,30 @@ struct ARow {
 template <class S, bool INTERIOR>
 __device__ inline void aissue_row(const StepParams& p, const AMarch& m, int y, bool live, ASlot<S>& sl, RowGeo& g) {
   g = row_geo(p, y);
-  unsigned off[9], offh[9];
+  const __amdgpu_buffer_rsrc_t in = buf_rsrc(m.f, live ? m.bytes : 0u);
   if (INTERIOR) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const int eyi = ey(i);
       const unsigned row = eyi == 1 ? g.bot : (eyi == -1 ? g.top : g.own);
       const unsigned rb = ((unsigned)i * m.N + row) * (unsigned)sizeof(S);
-      off[i] = rb + m.colB[i];
-      offh[i] = m.hl ? rb + m.colH[i] : m.bytes;
+      sl.raw[i] = BufIO<S>::load(in, m.colB[i], rb);
+      sl.rawh[i] = BufIO<S>::load(in, m.colH[i], rb);
     }
   } else {
+    unsigned off[9], offh[9];
     pull_offsets<S>(g, m.c, m.N, m.bytes, off);
     pull_offsets<S>(g, m.h, m.N, m.bytes, offh);
+    load_row<S>(in, off, sl.raw);
+    load_row<S>(in, offh, sl.rawh);
   }
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    off[i] = live ? off[i] : m.bytes;
-    offh[i] = live ? offh[i] : m.bytes;
-  }
-  load_row<S>(m.in, off, sl.raw);
-  load_row<S>(m.in, offh, sl.rawh);
   if constexpr (sizeof(S) == 4) {
     // every population pulled into this row was stored relative to the
     // puller's own offset: one offset per node
-    const bool rr = live && g.real;
-    sl.r.m = BufIO<float>::load(m.ref, rr ? (g.own + m.c.own) * 4u : m.refbytes);
-    sl.r.h = BufIO<float>::load(m.ref, (rr && m.h.real) ? (g.own + m.h.own) * 4u : m.refbytes);
+    const __amdgpu_buffer_rsrc_t rf =
+        buf_rsrc((const float*)m.f + (size_t)9 * m.N, (live && g.real) ? m.refbytes : 0u);
+    sl.r.m = BufIO<float>::load(rf, m.c.own * 4u, g.own * 4u);
+    sl.r.h = BufIO<float>::load(rf, m.href, g.own * 4u);
   }
 }
 
@@ -945,13 +955,27 @@ __device__ inline void arow_state(const StepParams& p, const AMarch& m, const AS
   t.psih = (t.g.real && m.h.real) ? psh : p.psi_solid;
 }
 
+// The kernel's parameters, read again from the kernel-argument segment (the
+// StepParams argument is the kernel's first, at offset 0).  The march calls it
+// once per row, and the empty asm hides that the address does not change, so
+// the ~30 constants of the step are scalar loads near their use instead of
+// registers held across the whole march; holding them exceeds the scalar
+// register file, and the compiler's spills cost a vector instruction per
+// use.
+typedef const __attribute__((address_space(4))) StepParams* KernargParams;
+__device__ inline const StepParams& kernarg_params() {
+  KernargParams kp = (KernargParams)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(kp));
+  return *(const StepParams*)kp;
+}
+
 // Collide and store row y (slot `s0`, state `t0`), with psi of rows y-1 (`tm`)
 // and y+1 (`t1`, finished here from slot `s1`); the loads of row y + AHEAD
 // go into slot `sn` first.
 template <class S, bool REDUCE, bool INTERIOR, int AHEAD>
-__device__ inline void amarch_row(const StepParams& p, const AMarch& m, int y, const ASlot<S>& s0,
-                                  const ASlot<S>& s1, ASlot<S>& sn, const ARow& tm, const ARow& t0, ARow& t1,
-                                  ARow& tn, double* acc) {
+__device__ inline void amarch_row(const AMarch& m, int y, const ASlot<S>& s0, const ASlot<S>& s1, ASlot<S>& sn,
+                                  const ARow& tm, const ARow& t0, ARow& t1, ARow& tn, double* acc) {
+  const StepParams& p = kernarg_params();
   aissue_row<S, INTERIOR>(p, m, y + AHEAD, y + AHEAD <= m.y1, sn, tn.g);
   arow_state<S>(p, m, s1, t1);
   // lane 0's west and lane 63's east neighbours are the halo columns, whose
@@ -981,11 +1005,11 @@ __device__ inline void amarch_row(const StepParams& p, const AMarch& m, int y, c
     for (int i = 0; i < 9; ++i) cd[i] = 0.0f;
   }
   const bool store = t0.g.real;
-  const unsigned k = t0.g.own + m.c.own;
+  const __amdgpu_buffer_rsrc_t out = buf_rsrc(m.fo, store ? m.bytes : 0u);
 #pragma unroll
   for (int i = 0; i < 9; ++i)
-    BufIO<S>::store(store_value<S>(d[i], wgt(i), (double)cd[i]), m.out,
-                    store ? ((unsigned)i * m.N + k) * (unsigned)sizeof(S) : m.bytes);
+    BufIO<S>::store(store_value<S>(d[i], wgt(i), (double)cd[i]), out, m.c.own * (unsigned)sizeof(S),
+                    ((unsigned)i * m.N + t0.g.own) * (unsigned)sizeof(S));
   if (REDUCE && store) {
     if (!INTERIOR) {
       double wx = 0.0, wy = 0.0;
@@ -1022,11 +1046,11 @@ __device__ inline void amarch(const StepParams& p, const AMarch& m, int y0, doub
     arow_state<S>(p, m, sc, tc);
     arow_state<S>(p, m, sa, ta);
     for (int y = y0; y < m.y1; y += 3) {
-      amarch_row<S, REDUCE, INTERIOR, 2>(p, m, y, sa, sb, sc, tc, ta, tb, tc, acc);
+      amarch_row<S, REDUCE, INTERIOR, 2>(m, y, sa, sb, sc, tc, ta, tb, tc, acc);
       if (y + 1 >= m.y1) break;
-      amarch_row<S, REDUCE, INTERIOR, 2>(p, m, y + 1, sb, sc, sa, ta, tb, tc, ta, acc);
+      amarch_row<S, REDUCE, INTERIOR, 2>(m, y + 1, sb, sc, sa, ta, tb, tc, ta, acc);
       if (y + 2 >= m.y1) break;
-      amarch_row<S, REDUCE, INTERIOR, 2>(p, m, y + 2, sc, sa, sb, tb, tc, ta, tb, acc);
+      amarch_row<S, REDUCE, INTERIOR, 2>(m, y + 2, sc, sa, sb, tb, tc, ta, tb, acc);
     }
   } else {
     ASlot<S> s0, s1, s2, s3;
@@ -1039,13 +1063,13 @@ __device__ inline void amarch(const StepParams& p, const AMarch& m, int y0, doub
     arow_state<S>(p, m, s0, t0);
     arow_state<S>(p, m, s1, t1);
     for (int y = y0; y < m.y1; y += 4) {
-      amarch_row<S, REDUCE, INTERIOR, 3>(p, m, y, s1, s2, s0, t0, t1, t2, t0, acc);
+      amarch_row<S, REDUCE, INTERIOR, 3>(m, y, s1, s2, s0, t0, t1, t2, t0, acc);
       if (y + 1 >= m.y1) break;
-      amarch_row<S, REDUCE, INTERIOR, 3>(p, m, y + 1, s2, s3, s1, t1, t2, t3, t1, acc);
+      amarch_row<S, REDUCE, INTERIOR, 3>(m, y + 1, s2, s3, s1, t1, t2, t3, t1, acc);
       if (y + 2 >= m.y1) break;
-      amarch_row<S, REDUCE, INTERIOR, 3>(p, m, y + 2, s3, s0, s2, t2, t3, t0, t2, acc);
+      amarch_row<S, REDUCE, INTERIOR, 3>(m, y + 2, s3, s0, s2, t2, t3, t0, t2, acc);
       if (y + 3 >= m.y1) break;
-      amarch_row<S, REDUCE, INTERIOR, 3>(p, m, y + 3, s0, s1, s3, t3, t0, t1, t3, acc);
+      amarch_row<S, REDUCE, INTERIOR, 3>(m, y + 3, s0, s1, s3, t3, t0, t1, t3, acc);
     }
   }
 }
@@ -1095,23 +1119,21 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
   AMarch m;
   m.N = (unsigned)p.nx * (unsigned)p.ny;
   m.bytes = 9u * m.N * (unsigned)sizeof(S);
-  m.in = __builtin_amdgcn_make_buffer_rsrc((void*)f, (short)0, (int)m.bytes, 0x00020000);
-  m.out = __builtin_amdgcn_make_buffer_rsrc((void*)fo, (short)0, (int)m.bytes, 0x00020000);
+  m.f = f;
+  m.fo = fo;
   const int x0 = strip * WAVE;
-  m.hl = lane == 0 || lane == WAVE - 1;
+  const bool hl = lane == 0 || lane == WAVE - 1;
   m.c = col_geo(p, x0 + lane, true);
-  m.h = col_geo(p, lane == 0 ? x0 - 1 : x0 + WAVE, m.hl);
+  m.h = col_geo(p, lane == 0 ? x0 - 1 : x0 + WAVE, hl);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const int exi = ex(i);
     m.colB[i] = (exi == 1 ? m.c.left : (exi == -1 ? m.c.right : m.c.own)) * (unsigned)sizeof(S);
-    m.colH[i] = (exi == 1 ? m.h.left : (exi == -1 ? m.h.right : m.h.own)) * (unsigned)sizeof(S);
+    m.colH[i] = hl ? (exi == 1 ? m.h.left : (exi == -1 ? m.h.right : m.h.own)) * (unsigned)sizeof(S) : m.colB[i];
   }
-  if constexpr (sizeof(S) == 4) {
-    // the reference plane follows the 9 population planes
-    m.refbytes = m.N * 4u;
-    m.ref = __builtin_amdgcn_make_buffer_rsrc((void*)(f + (size_t)9 * m.N), (short)0, (int)m.refbytes, 0x00020000);
-  }
+  // the reference plane follows the 9 population planes (float storage)
+  m.refbytes = m.N * 4u;
+  m.href = (m.h.real ? m.h.own : m.c.own) * 4u;
   const int y0 = seg * seg_len;
   m.y1 = min(y0 + seg_len, p.ny);
 
