@@ -197,7 +197,8 @@ __global__ void collide_kernel(StepParams p, const S* __restrict__ f, S* __restr
     double d[9];
     double wall[2] = {0.0, 0.0};
     double c;
-    pull_node<S>(p, f, mask, wall_u, x, y, d, REDUCE ? wall : nullptr, c);
+    float cd[9];
+    pull_node<S>(p, f, mask, wall_u, x, y, d, REDUCE ? wall : nullptr, c, cd);
     double drho, jx, jy;
     node_sums<S>(d, c, drho, jx, jy);
     double Sx, Sy;
@@ -206,10 +207,9 @@ __global__ void collide_kernel(StepParams p, const S* __restrict__ f, S* __restr
                  psi_at(p, psi, mask, x - 1, y - 1), psi_at(p, psi, mask, x + 1, y - 1), Sx, Sy);
     NodeMacro mac = collide_node<S>(p, d, c, drho, jx, jy, psi[k], Sx, Sy);
     const size_t plane = (size_t)p.nx * p.ny;
-    double cd[9];
-    dest_refs<S>(p, f, mask, x, y, cd);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) fo[(size_t)i * plane + k] = store_value<S>(d[i], wgt(i), cd[i]);
+    for (int i = 0; i < 9; ++i)
+      fo[(size_t)i * plane + k] = store_value<S>(d[i], wgt(i), sizeof(S) == 4 ? (double)cd[i] : 0.0);
     if (REDUCE) {
       bool bad;
       double rho = p.rho_ref + drho;
@@ -284,8 +284,8 @@ __global__ void fields_kernel(StepParams p, const S* __restrict__ f, const uint8
 template <class S>
 __device__ inline void strip_row_pull(const StepParams& p, const S* __restrict__ f, const uint8_t* __restrict__ mask,
                                       const double* __restrict__ wall_u, int x, int y, bool lane_in, double d[9],
-                                      double& c, double& drho, double& jx, double& jy, double& psi, bool& fluid,
-                                      bool& bad, double* wall) {
+                                      double& c, float* cd, double& drho, double& jx, double& jy, double& psi,
+                                      bool& fluid, bool& bad, double* wall) {
   // classify (x, y): outside the box across a wall, masked solid, or fluid
   int xw = 0, yw = 0;
   bool inside;
@@ -293,7 +293,7 @@ __device__ inline void strip_row_pull(const StepParams& p, const S* __restrict__
   fluid = !sol;
   bad = false;
   if (fluid) {
-    pull_node<S>(p, f, mask, wall_u, xw, yw, d, wall, c);
+    pull_node<S>(p, f, mask, wall_u, xw, yw, d, wall, c, cd);
     node_sums<S>(d, c, drho, jx, jy);
     psi = psi_of(p, p.rho_ref + drho, bad);
   } else {
@@ -329,6 +329,8 @@ __global__ __launch_bounds__(256) void fused_kernel(StepParams p, const S* __res
 
   double dc[9], dn[9];
   double cc, cn;
+  // float storage: offsets of the nodes that pull the current / next row's populations
+  float cdc[9], cdn[9];
   double drc, jxc, jyc, drn, jxn, jyn;
   double psm, psc, psn;
   bool flc, fln, badc, badn;
@@ -338,14 +340,15 @@ __global__ __launch_bounds__(256) void fused_kernel(StepParams p, const S* __res
   {
     double dtmp[9], ct, a, b, c;
     bool ftmp, btmp;
-    strip_row_pull<S>(p, f, mask, wall_u, x, y0 - 1, lane_in, dtmp, ct, a, b, c, psm, ftmp, btmp, nullptr);
+    strip_row_pull<S>(p, f, mask, wall_u, x, y0 - 1, lane_in, dtmp, ct, nullptr, a, b, c, psm, ftmp, btmp, nullptr);
   }
-  strip_row_pull<S>(p, f, mask, wall_u, x, y0, lane_in, dc, cc, drc, jxc, jyc, psc, flc, badc,
-                    REDUCE ? wallc : nullptr);
+  strip_row_pull<S>(p, f, mask, wall_u, x, y0, lane_in, dc, cc, sizeof(S) == 4 ? cdc : nullptr, drc, jxc, jyc, psc,
+                    flc, badc, REDUCE ? wallc : nullptr);
 
   for (int y = y0; y < y1; ++y) {
     walln[0] = walln[1] = 0.0;
-    strip_row_pull<S>(p, f, mask, wall_u, x, y + 1, lane_in, dn, cn, drn, jxn, jyn, psn, fln, badn,
+    strip_row_pull<S>(p, f, mask, wall_u, x, y + 1, lane_in, dn, cn, sizeof(S) == 4 ? cdn : nullptr, drn, jxn, jyn,
+                      psn, fln, badn,
                       (REDUCE && y + 1 < y1) ? walln : nullptr);
     // neighbours' psi through the wavefront (lanes 0 and 63 never collide)
     double pW = shfl_up1(psc), pE = shfl_down1(psc);
@@ -356,10 +359,9 @@ __global__ __launch_bounds__(256) void fused_kernel(StepParams p, const S* __res
       stencil_sums(pE, psn, pW, psm, pNE, pNW, pSW, pSE, Sx, Sy);
       NodeMacro mac = collide_node<S>(p, dc, cc, drc, jxc, jyc, psc, Sx, Sy);
       const size_t k = (size_t)y * p.nx + x;
-      double cd[9];
-      dest_refs<S>(p, f, mask, x, y, cd);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) fo[(size_t)i * plane + k] = store_value<S>(dc[i], wgt(i), cd[i]);
+      for (int i = 0; i < 9; ++i)
+        fo[(size_t)i * plane + k] = store_value<S>(dc[i], wgt(i), sizeof(S) == 4 ? (double)cdc[i] : 0.0);
       if (REDUCE) {
         acc[RED_WALLX] += wallc[0];
         acc[RED_WALLY] += wallc[1];
@@ -370,7 +372,10 @@ __global__ __launch_bounds__(256) void fused_kernel(StepParams p, const S* __res
     psm = psc;
     psc = psn;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) dc[i] = dn[i];
+    for (int i = 0; i < 9; ++i) {
+      dc[i] = dn[i];
+      cdc[i] = cdn[i];
+    }
     cc = cn;
     drc = drn;
     jxc = jxn;

@@ -180,43 +180,62 @@ __host__ __device__ inline void dest_refs(const StepParams& p, const S* __restri
 // dbar_opp(i)(x) (+ the moving-wall term) when x - e_i is solid, as
 // deviations from w_i (R + c) with c the node's reference offset (returned;
 // 0 for double storage).  When `wall` is non-null, accumulates the momentum
-// handed to the walls.
+// handed to the walls.  When `cdst` is non-null (float storage), also
+// returns the offsets of the nodes that will pull this node's post-collision
+// populations (the node x + e_i is the source of direction opp(i)).
 template <class S>
 __host__ __device__ inline void pull_node(const StepParams& p, const S* __restrict__ f, const uint8_t* __restrict__ mask,
                                           const double* __restrict__ wall_u, int x, int y, double d[9], double* wall,
-                                          double& c) {
+                                          double& c, float* cdst = nullptr) {
   const size_t plane = (size_t)p.nx * p.ny;
   const size_t self = (size_t)y * p.nx + x;
   // every population gathered here was stored relative to this node's offset
   const double c_self = ref_offset<S>(f, plane, self);
   c = c_self;
+  bool sol[9], ins[9];
+  size_t ks[9];
+  sol[0] = false;
+  ins[0] = true;
+  ks[0] = self;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    int xs, ys;
+    sol[i] = solid_at(p, mask, x - ex(i), y - ey(i), xs, ys, ins[i]);
+    ks[i] = (size_t)ys * p.nx + xs;
+  }
+  double cd[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) cd[i] = 0.0;
+  if constexpr (sizeof(S) == 4) {
+    if (cdst || wall_u) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const int j = opp(i);
+        cd[i] = sol[j] ? c_self : ref_offset<S>(f, plane, ks[j]);
+        if (cdst) cdst[i] = (float)cd[i];
+      }
+    }
+  }
   d[0] = (double)f[self];
   double rho_w = 0.0;
   bool have_rho_w = false;
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
-    int xs, ys;
-    bool inside;
-    bool sol = solid_at(p, mask, x - ex(i), y - ey(i), xs, ys, inside);
-    if (!sol) {
-      const size_t ks = (size_t)ys * p.nx + xs;
-      d[i] = (double)f[(size_t)i * plane + ks];
+    if (!sol[i]) {
+      d[i] = (double)f[(size_t)i * plane + ks[i]];
     } else {
       double v = (double)f[(size_t)opp(i) * plane + self];
       double mw = 0.0;
-      if (wall_u && inside) {
+      if (wall_u && ins[i]) {
         if (!have_rho_w) {
           // density of this node at the previous step: sum of its own fbar
-          double cd[9];
-          dest_refs<S>(p, f, mask, x, y, cd);
           double s = 0.0;
 #pragma unroll
           for (int q = 0; q < 9; ++q) s += (double)f[(size_t)q * plane + self] + wgt(q) * cd[q];
           rho_w = p.rho_ref + s;
           have_rho_w = true;
         }
-        size_t ks = (size_t)ys * p.nx + xs;
-        double eu = ex(i) * wall_u[ks] + ey(i) * wall_u[plane + ks];
+        double eu = ex(i) * wall_u[ks[i]] + ey(i) * wall_u[plane + ks[i]];
         mw = 6.0 * wgt(i) * rho_w * eu;
         v += mw;
       }
