@@ -255,8 +255,17 @@ int lbm_adjoint_backward(lbm_lattice* h, double* grad_rho0, double* grad_force, 
     e = hipMemcpyAsync(A, ck, sbytes, hipMemcpyDeviceToDevice, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(B, ck, sbytes, hipMemcpyDeviceToDevice, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "checkpoint copy");
+    const bool fused = replay_writes_traj(h);
     for (int64_t t = s0 + 1; t <= s1; ++t) {
       double* slot = traj + (size_t)(t - s0 - 1) * 4 * n;
+      if (fused) {
+        // the replayed step writes step t's trajectory itself (the last
+        // step's populations are not used)
+        e = step_between(h, A, B, 0, slot);
+        if (e != hipSuccess) return hip_fail(h, e, "replay step launch");
+        std::swap(A, B);
+        continue;
+      }
       e = fp64 ? pplbm::launch_traj<double>(h->prm, A, h->buf.mask, slot, h->stream)
                : pplbm::launch_traj<float>(h->prm, A, h->buf.mask, slot, h->stream);
       if (e != hipSuccess) return hip_fail(h, e, "replay launch");

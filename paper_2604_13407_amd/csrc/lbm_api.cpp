@@ -48,7 +48,13 @@ bool fast_path(const lbm_lattice* h) {
   return h->cfg.kernel == LBM_KERNEL_FUSED && !h->buf.mask && !h->buf.wall_u && bytes < 4294967040.0;
 }
 
-hipError_t step_between(lbm_lattice* h, const void* f_in, void* f_out, int reduce) {
+bool replay_writes_traj(const lbm_lattice* h) {
+  // the aligned strip kernel, with 32-bit byte offsets into the trajectory
+  return fast_path(h) && pplbm::aligned_strips(h->cfg.nx, 1) &&
+         32.0 * (double)h->cfg.nx * (double)h->cfg.ny < 4294967040.0;
+}
+
+hipError_t step_between(lbm_lattice* h, const void* f_in, void* f_out, int reduce, double* traj) {
   pplbm::StepLaunch L;
   L.f_in = f_in;
   L.f_out = f_out;
@@ -60,6 +66,7 @@ hipError_t step_between(lbm_lattice* h, const void* f_in, void* f_out, int reduc
   L.seg_len = h->seg_len;
   L.reduce = reduce;
   L.fast = fast_path(h) ? 1 : 0;
+  L.traj = traj;
   return (h->cfg.precision == LBM_FP64) ? pplbm::launch_step<double>(h->prm, L, h->stream)
                                         : pplbm::launch_step<float>(h->prm, L, h->stream);
 }

@@ -54,7 +54,11 @@ int hip_fail(lbm_lattice* h, hipError_t e, const char* what);
 bool config_ok(const lbm_config* c, std::string& why);
 // One step from f_in to f_out with the handle's kernels and launch shape;
 // reduce = 1 writes reduction partials (n_parts_of(h) of them).
-hipError_t step_between(lbm_lattice* h, const void* f_in, void* f_out, int reduce);
+// One step from f_in to f_out; `traj` (NULL, or [4][ny][nx] doubles: the
+// step's rho - rho_ref, j_x, j_y, psi) only where replay_writes_traj(h).
+hipError_t step_between(lbm_lattice* h, const void* f_in, void* f_out, int reduce, double* traj = nullptr);
+// Whether the step kernel can write the adjoint trajectory itself.
+bool replay_writes_traj(const lbm_lattice* h);
 int n_parts_of(const lbm_lattice* h);
 void* state_ptr(lbm_lattice* h, int which);
 void fill_record(const double* v, int64_t step, lbm_reduction* r);

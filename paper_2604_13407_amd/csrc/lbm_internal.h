@@ -19,6 +19,8 @@ struct StepLaunch {
   int seg_len;        // fused: rows per wavefront
   int reduce;         // 1: write reduction partials this step
   int fast;           // fused: use the specialised strip kernel (no mask, no moving walls, 32-bit offsets)
+  double* traj;       // adjoint replay: also write rho - rho_ref, j_x, j_y, psi per node ([4][ny][nx]);
+                      // aligned strip kernel only, without reductions; NULL otherwise
 };
 
 int two_pass_blocks(int nx, int ny);

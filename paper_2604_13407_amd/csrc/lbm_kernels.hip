@@ -843,6 +843,7 @@ struct AMarch {
   // float storage: the reference plane, and the column byte offset of the
   // halo column's reference (the lane's own where there is none)
   unsigned refbytes, href;
+  double* traj;  // replay: rho - rho_ref, j_x, j_y, psi of every stored node, [4][ny][nx]
 };
 
 // Reference offsets of one row (float storage): c at the lane's column (m)
@@ -977,7 +978,7 @@ __device__ inline const StepParams& kernarg_params() {
 // Collide and store row y (slot `s0`, state `t0`), with psi of rows y-1 (`tm`)
 // and y+1 (`t1`, finished here from slot `s1`); the loads of row y + AHEAD
 // go into slot `sn` first.
-template <class S, bool REDUCE, bool INTERIOR, int AHEAD>
+template <class S, bool REDUCE, bool TRAJ, bool INTERIOR, int AHEAD>
 __device__ inline void amarch_row(const AMarch& m, int y, const ASlot<S>& s0, const ASlot<S>& s1, ASlot<S>& sn,
                                   const ARow& tm, const ARow& t0, ARow& t1, ARow& tn, double* acc) {
   const StepParams& p = kernarg_params();
@@ -1015,6 +1016,13 @@ __device__ inline void amarch_row(const AMarch& m, int y, const ASlot<S>& s0, co
   for (int i = 0; i < 9; ++i)
     BufIO<S>::store(store_value<S>(d[i], wgt(i), (double)cd[i]), out, m.c.own * (unsigned)sizeof(S),
                     ((unsigned)i * m.N + t0.g.own) * (unsigned)sizeof(S));
+  if (TRAJ) {
+    // the replayed step's pulled-state quantities, as the adjoint reads them
+    const __amdgpu_buffer_rsrc_t tr = buf_rsrc(m.traj, store ? 4u * m.N * 8u : 0u);
+    const double tv[4] = {t0.drho, t0.jx, t0.jy, t0.psi};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) BufIO<double>::store(tv[q], tr, m.c.own * 8u, ((unsigned)q * m.N + t0.g.own) * 8u);
+  }
   if (REDUCE && store) {
     if (!INTERIOR) {
       double wx = 0.0, wy = 0.0;
@@ -1039,7 +1047,7 @@ __device__ inline void amarch_row(const AMarch& m, int y, const ASlot<S>& s0, co
 
 // The march over rows y0 .. y1-1.  Float storage keeps three row slots (row
 // y+2 in flight while row y collides), double storage four (rows y+2, y+3).
-template <class S, bool REDUCE, bool INTERIOR>
+template <class S, bool REDUCE, bool TRAJ, bool INTERIOR>
 __device__ inline void amarch(const StepParams& p, const AMarch& m, int y0, double* acc) {
   if (sizeof(S) == 4) {
     ASlot<S> sa, sb, sc;
@@ -1051,11 +1059,11 @@ __device__ inline void amarch(const StepParams& p, const AMarch& m, int y0, doub
     arow_state<S>(p, m, sc, tc);
     arow_state<S>(p, m, sa, ta);
     for (int y = y0; y < m.y1; y += 3) {
-      amarch_row<S, REDUCE, INTERIOR, 2>(m, y, sa, sb, sc, tc, ta, tb, tc, acc);
+      amarch_row<S, REDUCE, TRAJ, INTERIOR, 2>(m, y, sa, sb, sc, tc, ta, tb, tc, acc);
       if (y + 1 >= m.y1) break;
-      amarch_row<S, REDUCE, INTERIOR, 2>(m, y + 1, sb, sc, sa, ta, tb, tc, ta, acc);
+      amarch_row<S, REDUCE, TRAJ, INTERIOR, 2>(m, y + 1, sb, sc, sa, ta, tb, tc, ta, acc);
       if (y + 2 >= m.y1) break;
-      amarch_row<S, REDUCE, INTERIOR, 2>(m, y + 2, sc, sa, sb, tb, tc, ta, tb, acc);
+      amarch_row<S, REDUCE, TRAJ, INTERIOR, 2>(m, y + 2, sc, sa, sb, tb, tc, ta, tb, acc);
     }
   } else {
     ASlot<S> s0, s1, s2, s3;
@@ -1068,13 +1076,13 @@ __device__ inline void amarch(const StepParams& p, const AMarch& m, int y0, doub
     arow_state<S>(p, m, s0, t0);
     arow_state<S>(p, m, s1, t1);
     for (int y = y0; y < m.y1; y += 4) {
-      amarch_row<S, REDUCE, INTERIOR, 3>(m, y, s1, s2, s0, t0, t1, t2, t0, acc);
+      amarch_row<S, REDUCE, TRAJ, INTERIOR, 3>(m, y, s1, s2, s0, t0, t1, t2, t0, acc);
       if (y + 1 >= m.y1) break;
-      amarch_row<S, REDUCE, INTERIOR, 3>(m, y + 1, s2, s3, s1, t1, t2, t3, t1, acc);
+      amarch_row<S, REDUCE, TRAJ, INTERIOR, 3>(m, y + 1, s2, s3, s1, t1, t2, t3, t1, acc);
       if (y + 2 >= m.y1) break;
-      amarch_row<S, REDUCE, INTERIOR, 3>(m, y + 2, s3, s0, s2, t2, t3, t0, t2, acc);
+      amarch_row<S, REDUCE, TRAJ, INTERIOR, 3>(m, y + 2, s3, s0, s2, t2, t3, t0, t2, acc);
       if (y + 3 >= m.y1) break;
-      amarch_row<S, REDUCE, INTERIOR, 3>(m, y + 3, s0, s1, s3, t3, t0, t1, t3, acc);
+      amarch_row<S, REDUCE, TRAJ, INTERIOR, 3>(m, y + 3, s0, s1, s3, t3, t0, t1, t3, acc);
     }
   }
 }
@@ -1108,10 +1116,10 @@ __device__ inline ColGeo col_geo(const StepParams& p, int x, bool want) {
   return c;
 }
 
-template <class S, bool REDUCE>
+template <class S, bool REDUCE, bool TRAJ>
 __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __restrict__ f, S* __restrict__ fo,
                                                       int n_strips, int seg_len, int n_segs, int groups, int per_xcd,
-                                                      double* __restrict__ partials) {
+                                                      double* __restrict__ partials, double* __restrict__ traj) {
   const int b = blockIdx.x;
   const int L = (b & 7) * per_xcd + (b >> 3);
   const int seg = L / groups;
@@ -1139,6 +1147,7 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
   // the reference plane follows the 9 population planes (float storage)
   m.refbytes = m.N * 4u;
   m.href = (m.h.real ? m.h.own : m.c.own) * 4u;
+  m.traj = traj;
   const int y0 = seg * seg_len;
   m.y1 = min(y0 + seg_len, p.ny);
 
@@ -1150,9 +1159,9 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
   // without wrapping) of y-periodic lattices take the select-free offsets.
   const bool interior = p.periodic_y && x0 >= 2 && x0 + WAVE + 1 <= p.nx - 1;
   if (interior)
-    amarch<S, REDUCE, true>(p, m, y0, acc);
+    amarch<S, REDUCE, TRAJ, true>(p, m, y0, acc);
   else
-    amarch<S, REDUCE, false>(p, m, y0, acc);
+    amarch<S, REDUCE, TRAJ, false>(p, m, y0, acc);
 
   if (REDUCE) {
 #pragma unroll
@@ -1238,6 +1247,8 @@ template <class S>
 hipError_t launch_step(const StepParams& p, const StepLaunch& L, hipStream_t st) {
   const S* f = (const S*)L.f_in;
   S* fo = (S*)L.f_out;
+  // only the aligned strip kernel writes the trajectory
+  if (L.traj && !(L.kernel == 0 && aligned_strips(p.nx, L.fast))) return hipErrorNotSupported;
   if (L.kernel == 1) {
     dim3 blk(64, 4);
     dim3 grd = node_grid(p, blk);
@@ -1254,12 +1265,16 @@ hipError_t launch_step(const StepParams& p, const StepLaunch& L, hipStream_t st)
     int groups = (n_strips + 3) / 4;
     int total = groups * n_segs;
     int per_xcd = (total + 7) / 8;
-    if (L.reduce)
-      hipLaunchKernelGGL((aligned_kernel<S, true>), dim3(8 * per_xcd), dim3(256), 0, st, p, f, fo, n_strips,
-                         L.seg_len, n_segs, groups, per_xcd, L.partials);
+    if (L.traj && L.reduce) return hipErrorInvalidValue;
+    if (L.traj)
+      hipLaunchKernelGGL((aligned_kernel<S, false, true>), dim3(8 * per_xcd), dim3(256), 0, st, p, f, fo, n_strips,
+                         L.seg_len, n_segs, groups, per_xcd, L.partials, L.traj);
+    else if (L.reduce)
+      hipLaunchKernelGGL((aligned_kernel<S, true, false>), dim3(8 * per_xcd), dim3(256), 0, st, p, f, fo, n_strips,
+                         L.seg_len, n_segs, groups, per_xcd, L.partials, nullptr);
     else
-      hipLaunchKernelGGL((aligned_kernel<S, false>), dim3(8 * per_xcd), dim3(256), 0, st, p, f, fo, n_strips,
-                         L.seg_len, n_segs, groups, per_xcd, L.partials);
+      hipLaunchKernelGGL((aligned_kernel<S, false, false>), dim3(8 * per_xcd), dim3(256), 0, st, p, f, fo, n_strips,
+                         L.seg_len, n_segs, groups, per_xcd, L.partials, nullptr);
   } else if (L.fast && launch_fast62<S>(p, L, st)) {
     // launched: the 62-column strip kernel (double storage, widths not a multiple of 64)
   } else {
