@@ -129,7 +129,8 @@ int default_seg_len(const lbm_lattice* h) {
   const int nx = h->cfg.nx, ny = std::max(h->cfg.ny, 1);
   int n_strips, n_segs;
   const bool aligned = pplbm::aligned_strips(nx, fast_path(h) ? 1 : 0);
-  const long target = h->cfg.precision == LBM_FP64 ? 1024 : 2048;
+  // enough wavefronts for ~2 (FP64) or ~2.5 (FP32, which fits 3) per SIMD of the 1,024
+  const long target = h->cfg.precision == LBM_FP64 ? 1024 : 2560;
   for (int rows : {24, 16, 12, 8, 6}) {
     pplbm::fused_shape(nx, ny, rows, aligned, &n_strips, &n_segs);
     if ((long)n_strips * n_segs >= target) return std::min(rows, ny);
