@@ -78,11 +78,12 @@ __global__ void adj_local_kernel(StepParams p, AdjStepArgs a) {
   block_add(part, 2, a.param_acc, blockIdx.x, 2);
 }
 
+template <class L>
 __global__ void adj_psi_kernel(StepParams p, AdjStepArgs a) {
   int x, y;
   node_xy(p, x, y);
   if (x >= p.nx || y >= p.ny) return;
-  adj_psi_node(p, a, x, y);
+  adj_psi_node<L>(p, a, x, y);
 }
 
 template <class L>
@@ -165,7 +166,7 @@ hipError_t launch_traj(const StepParams& p, const void* f, const uint8_t* mask, 
 template <class L>
 hipError_t launch_adj_step(const StepParams& p, const AdjStepArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(adj_local_kernel<L>, agrid(p), ABLOCK, 0, st, p, a);
-  hipLaunchKernelGGL(adj_psi_kernel, agrid(p), ABLOCK, 0, st, p, a);
+  hipLaunchKernelGGL(adj_psi_kernel<L>, agrid(p), ABLOCK, 0, st, p, a);
   return hipGetLastError();
 }
 

@@ -8,16 +8,17 @@
 
 namespace pplbm {
 
-// One reverse step n.  Arrays are [plane][ny][nx]; D holds elements of type
-// L (float for float storage, double for double storage), the rest doubles.
+// One reverse step n.  Arrays are [plane][ny][nx]; D, R and T hold elements
+// of type L (float for float storage, double for double storage), the rest
+// doubles.
 struct AdjStepArgs {
   const uint8_t* mask;      // solid nodes, or NULL
   const double* traj;       // [4]: rho - rho_ref, j_x, j_y, psi of step n's pulled state
   const void* D_next;       // [9] L: dL/d(pulled populations) of step n + 1 through its collision
-  const double* R_next;     // [1]: psi'(rho) dL/dpsi of step n + 1
+  const void* R_next;       // [1] L: psi'(rho) dL/dpsi of step n + 1
   void* D;                  // [9] L: output for step n
-  double* T;                // [3]: dL/dpsi_c, dL/dS_x, dL/dS_y of step n (scratch)
-  double* R;                // [1]: output for step n
+  void* T;                  // [3] L: dL/dpsi_c, dL/dS_x, dL/dS_y of step n (scratch)
+  void* R;                  // [1] L: output for step n
   double* param_acc;        // [blocks][2]: running dL/dG, dL/d|F_ext| per block
   const double* u_target;   // velocity-error loss: target u_x, [ny][nx]
   int32_t have_next;        // 0 for the last step (lambda^N = 0)

@@ -241,9 +241,10 @@ template <class L>
 __host__ __device__ inline double lambda_of(const StepParams& p, const AdjStepArgs& a, const Nbrs& nb, int i) {
   const size_t N = (size_t)p.nx * p.ny;
   const L* Dn = static_cast<const L*>(a.D_next);
+  const L* Rn = static_cast<const L*>(a.R_next);
   const size_t k = nb.k[0];
-  if (i != 0 && nb.fluid[i]) return (double)Dn[(size_t)i * N + nb.k[i]] + a.R_next[nb.k[i]];
-  return (double)Dn[(size_t)opp(i) * N + k] + a.R_next[k];
+  if (i != 0 && nb.fluid[i]) return (double)Dn[(size_t)i * N + nb.k[i]] + (double)Rn[nb.k[i]];
+  return (double)Dn[(size_t)opp(i) * N + k] + (double)Rn[k];
 }
 
 // Replay: rho - rho_ref, j and psi of the state f pulled to node (x, y)
@@ -276,7 +277,7 @@ __host__ __device__ inline double psi_nbr(const StepParams& p, const double* __r
 
 // Reverse of node (x, y)'s step n: gathers lambda^n from step n + 1, adds
 // the loss's direct sensitivities at step n, reverses the collision.  Writes
-// D^n (rounded to L) and T^n of the node; adds its dL/dG, dL/d|F_ext| shares
+// D^n and T^n of the node (rounded to L); adds its dL/dG, dL/d|F_ext| shares
 // to part[0..1].
 template <class L>
 __host__ __device__ inline void adj_local_node(const StepParams& p, const AdjStepArgs& a, int x, int y,
@@ -323,32 +324,38 @@ __host__ __device__ inline void adj_local_node(const StepParams& p, const AdjSte
     collide_node_adjoint(p, drho, jx, jy, pc, Sx, Sy, ob, ls, o);
 #pragma unroll
     for (int i = 0; i < 9; ++i) static_cast<L*>(a.D)[(size_t)i * N + k] = (L)o.dd[i];
-    a.T[k] = o.psi_c;
-    a.T[N + k] = o.Sx;
-    a.T[2 * N + k] = o.Sy;
+    L* T = static_cast<L*>(a.T);
+    T[k] = (L)o.psi_c;
+    T[N + k] = (L)o.Sx;
+    T[2 * N + k] = (L)o.Sy;
     part[0] += o.G;
     part[1] += o.g;
   } else {
 #pragma unroll
     for (int i = 0; i < 9; ++i) static_cast<L*>(a.D)[(size_t)i * N + k] = (L)0;
-    a.T[k] = 0.0;
-    a.T[N + k] = 0.0;
-    a.T[2 * N + k] = 0.0;
+    L* T = static_cast<L*>(a.T);
+    T[k] = (L)0;
+    T[N + k] = (L)0;
+    T[2 * N + k] = (L)0;
   }
 }
 
-// dL/dpsi(x) = T_c(x) + sum_k w_k e_k . T_S(x - e_k), and R^n(x) = psi'(rho) dL/dpsi.
+// dL/dpsi(x) = T_c(x) + sum_k w_k e_k . T_S(x - e_k), and R^n(x) = psi'(rho) dL/dpsi
+// (T and R of type L).
+template <class L>
 __host__ __device__ inline void adj_psi_node(const StepParams& p, const AdjStepArgs& a, int x, int y) {
   const size_t N = (size_t)p.nx * p.ny;
   const size_t k = (size_t)y * p.nx + x;
+  const L* T = static_cast<const L*>(a.T);
+  L* R = static_cast<L*>(a.R);
   if (a.mask && a.mask[k]) {
-    a.R[k] = 0.0;
+    R[k] = (L)0;
     return;
   }
   // psi(x) enters S(x - e_i) = S(x + e_opp(i)) with weight w_i e_i
   Nbrs nb;
   neighbours(p, a.mask, x, y, nb);
-  double pb = a.T[k];
+  double pb = (double)T[k];
   const double w1 = 1.0 / 3.0, w2 = 1.0 / 12.0;
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
@@ -356,11 +363,11 @@ __host__ __device__ inline void adj_psi_node(const StepParams& p, const AdjStepA
     if (nb.fluid[o]) {
       const size_t ks = nb.k[o];
       const double w = i <= 4 ? w1 : w2;
-      pb += w * (ex(i) * a.T[N + ks] + ey(i) * a.T[2 * N + ks]);
+      pb += w * (ex(i) * (double)T[N + ks] + ey(i) * (double)T[2 * N + ks]);
     }
   }
   const double r = p.rho_ref + a.traj[k];
-  a.R[k] = dpsi_drho(p, r, a.traj[3 * N + k]) * pb;
+  R[k] = (L)(dpsi_drho(p, r, a.traj[3 * N + k]) * pb);
 }
 
 // dL/drho0(x) = sum_i w_i lambda^0_i(x), since fbar^0_i = w_i rho0 at rest
