@@ -237,7 +237,8 @@ int lbm_rereference(lbm_lattice* h);
  * gravity (direction held fixed) and the interaction strength G.  They are
  * computed in double for both precisions; for LBM_FP32_DEV they are those of
  * the run as stored (the linearisation point is the FP32 trajectory) and the
- * per-step adjoint of the pulled populations is stored in float.
+ * per-step adjoint scratch (of the pulled populations, of psi and of the
+ * stencil sums) is stored in float.
  * Memory: the forward pass saves fbar every checkpoint_every steps; the
  * backward pass replays each segment from its checkpoint, keeping
  * rho - rho_ref, j and psi of every step of the segment (32 bytes per node and
