@@ -18,14 +18,15 @@
  *    collides.  "Macroscopic fields of the current state" are the pre-collision
  *    fields the next step would use.
  *  - Precision LBM_FP64 stores f in double.  LBM_FP32_DEV stores, in float,
- *    each population relative to its node's reference density:
- *    s_i(x) = f_i(x) - w_i * rhat(x), with rhat(x) = rho_ref + c(x) and the
- *    offset c kept as a tenth float plane of the population array (set from
- *    the initial density; see lbm_rereference).  Deviations from a node's own
- *    density are small in liquid and vapour alike, so the rounding of the
- *    stored values stays small where a uniform reference would not.  Both
- *    precisions compute the step in double (each population is rounded once
- *    when stored) and reduce in double.
+ *    each post-collision population relative to the reference density of the
+ *    node that will pull it: s_i(x) = f_i(x) - w_i * rhat(x + e_i) (rhat(x)
+ *    when x + e_i is solid or beyond a wall), with rhat = rho_ref + c and the
+ *    offsets c kept as 16-bit floats in the first half of a tenth plane of the
+ *    population array (set from the initial density; see lbm_rereference;
+ *    the plane's second half is zero).  The stored deviations stay small in
+ *    liquid and vapour alike, so their rounding stays small where a uniform
+ *    reference would not.  Both precisions compute the step in double (each
+ *    population is rounded once when stored) and reduce in double.
  *  - Ownership: the caller allocates and frees every device buffer (the
  *    population arrays, the workspace, the mask, the wall velocities and all
  *    outputs).  The library never allocates or frees device memory; it keeps

@@ -52,21 +52,25 @@ __global__ void init_kernel(StepParams p, const double* __restrict__ rho0, const
   double v = uy0 ? uy0[k] : 0.0;
   double usq = u * u + v * v;
   // float storage: every node's reference offset is c = rhat - rho_ref with
-  // rhat its initial density (as a float); population i is stored relative
-  // to the offset of the node that pulls it (x + e_i, or x across a wall)
+  // rhat its initial density (as a 16-bit float); population i is stored
+  // relative to the offset of the node that pulls it (x + e_i, or x across a
+  // wall)
   double cd[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) cd[i] = 0.0;
   if constexpr (sizeof(S) == 4) {
-    const float cf = (float)(r - p.rho_ref);
-    fa[9 * plane + k] = cf;
-    fb[9 * plane + k] = cf;
+    const RefT cf = (RefT)(r - p.rho_ref);
+    ref_plane(fa, plane)[k] = cf;
+    ref_plane(fb, plane)[k] = cf;
+    // the plane's unused second half is zero, so the whole state is defined
+    ref_plane(fa, plane)[plane + k] = (RefT)0;
+    ref_plane(fb, plane)[plane + k] = (RefT)0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       int xd, yd;
       bool inside;
       const bool sol = solid_at(p, mask, x + ex(i), y + ey(i), xd, yd, inside);
-      cd[i] = (double)(sol ? cf : (float)(rho0[(size_t)yd * p.nx + xd] - p.rho_ref));
+      cd[i] = (double)(sol ? cf : (RefT)(rho0[(size_t)yd * p.nx + xd] - p.rho_ref));
     }
   }
 #pragma unroll
@@ -93,7 +97,7 @@ __global__ void reref_new_kernel(StepParams p, const float* __restrict__ fa, flo
   const size_t plane = (size_t)p.nx * p.ny;
   const size_t k = (size_t)y * p.nx + x;
   if (mask && mask[k]) {
-    fb[9 * plane + k] = fa[9 * plane + k];
+    ref_plane(fb, plane)[k] = ref_plane(fa, plane)[k];
     return;
   }
   double cd[9];
@@ -101,7 +105,7 @@ __global__ void reref_new_kernel(StepParams p, const float* __restrict__ fa, flo
   double s = 0.0;
 #pragma unroll
   for (int i = 0; i < 9; ++i) s += (double)fa[(size_t)i * plane + k] + wgt(i) * cd[i];
-  fb[9 * plane + k] = (float)s;
+  ref_plane(fb, plane)[k] = (RefT)s;
 }
 
 __global__ void reref_shift_kernel(StepParams p, float* __restrict__ fa, float* __restrict__ fb, const uint8_t* mask) {
@@ -128,7 +132,7 @@ __global__ void reref_copy_kernel(StepParams p, float* __restrict__ fa, const fl
   if (x >= p.nx || y >= p.ny) return;
   const size_t plane = (size_t)p.nx * p.ny;
   const size_t k = (size_t)y * p.nx + x;
-  fa[9 * plane + k] = fb[9 * plane + k];
+  ref_plane(fa, plane)[k] = ref_plane(fb, plane)[k];
 }
 
 // ------------------------------------------------------------------ two-pass: psi
@@ -434,6 +438,11 @@ struct BufIO<double> {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)byte_off, (int)soff, 0);
   }
 };
+
+// A 16-bit float reference offset, widened.
+__device__ inline float load_ref16(__amdgpu_buffer_rsrc_t r, unsigned byte_off, unsigned soff) {
+  return (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)byte_off, (int)soff, 0));
+}
 
 // A buffer resource over `bytes` bytes at `base`; 0 bytes makes every access
 // out of range (loads return 0, stores are dropped).
@@ -892,8 +901,8 @@ __device__ inline void aissue_row(const StepParams& p, const AMarch& m, int y, b
     // puller's own offset: one offset per node
     const __amdgpu_buffer_rsrc_t rf =
         buf_rsrc((const float*)m.f + (size_t)9 * m.N, (live && g.real) ? m.refbytes : 0u);
-    sl.r.m = BufIO<float>::load(rf, m.c.own * 4u, g.own * 4u);
-    sl.r.h = BufIO<float>::load(rf, m.href, g.own * 4u);
+    sl.r.m = load_ref16(rf, m.c.own * 2u, g.own * 2u);
+    sl.r.h = load_ref16(rf, m.href, g.own * 2u);
   }
 }
 
@@ -1145,8 +1154,8 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
     m.colH[i] = hl ? (exi == 1 ? m.h.left : (exi == -1 ? m.h.right : m.h.own)) * (unsigned)sizeof(S) : m.colB[i];
   }
   // the reference plane follows the 9 population planes (float storage)
-  m.refbytes = m.N * 4u;
-  m.href = (m.h.real ? m.h.own : m.c.own) * 4u;
+  m.refbytes = m.N * 2u;
+  m.href = (m.h.real ? m.h.own : m.c.own) * 2u;
   m.traj = traj;
   const int y0 = seg * seg_len;
   m.y1 = min(y0 + seg_len, p.ny);

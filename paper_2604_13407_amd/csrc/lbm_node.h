@@ -13,8 +13,8 @@
 // that will pull it: s_i(x) = fbar_i(x) - w_i rhat(x + e_i), or - w_i rhat(x)
 // when x + e_i is solid or beyond a wall (the population then returns to x by
 // bounce-back).  The per-node reference density rhat = R + c has its offset c
-// held as a tenth float plane of the population array (the initial density,
-// unless re-referenced).  A pull at x therefore adds the same w_i c(x) to
+// held in a tenth plane of the population array (the initial density, unless
+// re-referenced; see ref_plane).  A pull at x therefore adds the same w_i c(x) to
 // every population it gathers, and the store at x subtracts the offsets of
 // its 8 neighbours.  The stored values stay small in liquid and vapour alike
 // (at an interface they are of the order of the density step between two
@@ -125,18 +125,31 @@ __host__ __device__ inline bool solid_at(const StepParams& p, const uint8_t* __r
   return mask ? (mask[(size_t)y * p.nx + x] != 0) : false;
 }
 
-// Planes of a population array: 9 populations, plus the reference plane c for
-// float storage.
+// Planes of a population array: 9 populations, plus the reference plane for
+// float storage, whose first half holds every node's offset c as a 16-bit
+// float (any representable c serves as a reference; 11 significant bits keep
+// the stored deviations small, and the plane costs 2 bytes per node to read).
 template <class S>
 __host__ __device__ constexpr int state_planes() {
   return sizeof(S) == 4 ? 10 : 9;
+}
+
+typedef _Float16 RefT;
+
+template <class S>
+__host__ __device__ inline RefT* ref_plane(S* f, size_t plane) {
+  return (RefT*)(f + 9 * plane);
+}
+template <class S>
+__host__ __device__ inline const RefT* ref_plane(const S* f, size_t plane) {
+  return (const RefT*)(f + 9 * plane);
 }
 
 // The reference offset c(k) of node k (0 for double storage).
 template <class S>
 __host__ __device__ inline double ref_offset(const S* __restrict__ f, size_t plane, size_t k) {
   if constexpr (sizeof(S) == 4) {
-    return (double)f[9 * plane + k];
+    return (double)ref_plane(f, plane)[k];
   } else {
     return 0.0;
   }

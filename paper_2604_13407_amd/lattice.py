@@ -248,7 +248,7 @@ class Lattice:
 
     def state(self) -> torch.Tensor:
         """The array that holds the current state: 9 population planes (FP32_DEV: stored
-        relative to each node's reference density, which is the tenth plane)."""
+        relative to the reference densities whose offsets the tenth plane holds)."""
         p = C.c_void_p(0)
         self._check(lib().lbm_state_ptr(self.h, C.byref(p)), self.h)
         return self.f_a if p.value == self.f_a.data_ptr() else self.f_b
