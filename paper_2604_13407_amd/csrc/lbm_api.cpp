@@ -72,11 +72,16 @@ hipError_t step_between(lbm_lattice* h, const void* f_in, void* f_out, int reduc
 }
 
 int n_parts_of(const lbm_lattice* h) {
-  if (h->cfg.kernel == LBM_KERNEL_TWO_PASS) return pplbm::two_pass_blocks(h->cfg.nx, h->cfg.ny);
-  int n_strips, n_segs;
-  pplbm::fused_shape(h->cfg.nx, h->cfg.ny, h->seg_len, pplbm::aligned_strips(h->cfg.nx, fast_path(h) ? 1 : 0),
-                     &n_strips, &n_segs);
-  return n_strips * n_segs;
+  const int nx = h->cfg.nx, ny = h->cfg.ny;
+  if (h->cfg.kernel == LBM_KERNEL_TWO_PASS) return pplbm::two_pass_blocks(nx, ny);
+  // the fused kernels, as launch_step picks them
+  const bool fast = fast_path(h);
+  if (fast && (pplbm::aligned_strips(nx, 1) || h->cfg.precision == LBM_FP64)) {
+    int n_strips, n_segs;
+    pplbm::fused_shape(nx, ny, h->seg_len, pplbm::aligned_strips(nx, 1), &n_strips, &n_segs);
+    return n_strips * n_segs;
+  }
+  return pplbm::tile_blocks(nx, ny);
 }
 
 void* state_ptr(lbm_lattice* h, int which) { return which == 0 ? h->buf.f_a : h->buf.f_b; }
@@ -143,7 +148,8 @@ size_t max_parts_for(const lbm_config* c) {
   pplbm::fused_shape(c->nx, c->ny, kMinSegLen, false, &n_strips, &n_segs);  // the larger count
   size_t fused = (size_t)n_strips * n_segs;
   size_t two = (size_t)pplbm::two_pass_blocks(c->nx, c->ny);
-  return std::max(fused, two);
+  size_t tiles = (size_t)pplbm::tile_blocks(c->nx, c->ny);
+  return std::max(fused, std::max(two, tiles));
 }
 
 struct Layout {

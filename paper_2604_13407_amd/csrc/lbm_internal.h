@@ -24,6 +24,9 @@ struct StepLaunch {
 };
 
 int two_pass_blocks(int nx, int ny);
+// Blocks (one reduction record each) of the fused tile kernel, which takes the
+// lattices the strip kernels do not.
+int tile_blocks(int nx, int ny);
 // Whether the step runs the aligned 64-column strip kernel (fast path on a
 // width that is a multiple of 64), and the strip/segment counts of the fused
 // kernels (one reduction record per strip and segment).

@@ -168,8 +168,8 @@ __device__ inline double psi_at(const StepParams& p, const double* __restrict__ 
 // Per-block deterministic reduction of acc[RED_COUNT] -> partials[block].
 __device__ inline void block_reduce_store(double* acc, double* __restrict__ partials, int block_id) {
   __shared__ double lds[RED_COUNT][16];
-  const int lane = threadIdx.x % WAVE;
   const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const int lane = tid % WAVE;
   const int wid = tid / WAVE;
   const int nw = (blockDim.x * blockDim.y) / WAVE;
 #pragma unroll
@@ -278,124 +278,110 @@ __global__ void fields_kernel(StepParams p, const S* __restrict__ f, const uint8
   if (reduce) block_reduce_store(acc, partials, blockIdx.y * gridDim.x + blockIdx.x);
 }
 
-// ------------------------------------------------------------------ fused strip kernel
+// ------------------------------------------------------------------ fused tile kernel
 //
-// Lane l of a wavefront holds column x = x0 - 1 + l; lanes 1..62 are the
-// strip's own columns, lanes 0 and 63 are halo columns that only supply psi.
-// The wave computes rows y0..y1-1 and also pulls rows y0-1 and y1 (halo rows)
-// for their psi.  Row pipeline: row r is pulled, summed and given psi; once
-// psi of row r+1 exists, row r collides and is stored.
-template <class S>
-__device__ inline void strip_row_pull(const StepParams& p, const S* __restrict__ f, const uint8_t* __restrict__ mask,
-                                      const double* __restrict__ wall_u, int x, int y, bool lane_in, double d[9],
-                                      double& c, float* cd, double& drho, double& jx, double& jy, double& psi,
-                                      bool& fluid, bool& bad, double* wall) {
-  // classify (x, y): outside the box across a wall, masked solid, or fluid
-  int xw = 0, yw = 0;
-  bool inside;
-  bool sol = !lane_in || solid_at(p, mask, x, y, xw, yw, inside);
-  fluid = !sol;
-  bad = false;
-  if (fluid) {
-    pull_node<S>(p, f, mask, wall_u, xw, yw, d, wall, c, cd);
-    node_sums<S>(d, c, drho, jx, jy);
-    psi = psi_of(p, p.rho_ref + drho, bad);
+// The fused step for every lattice the strip kernels do not take (solid
+// masks, moving walls, widths that are not a multiple of 64 with float
+// storage): a block of 32 x 8 threads owns a 32 x 8 tile, one node per
+// thread.  Each thread pulls its node (keeping the pulled populations in
+// registers), computes psi and writes it to an LDS tile with a one-node ring;
+// 84 threads also compute psi of the ring's nodes.  After one barrier every
+// node collides with its neighbours' psi from LDS and is stored.  Many small
+// blocks keep enough loads in flight on lattices with solid nodes, where the
+// per-node pull is a chain of dependent loads.
+constexpr int TILE_X = 32, TILE_Y = 8;
+constexpr int TILE_HX = TILE_X + 2, TILE_HY = TILE_Y + 2;
+constexpr int TILE_RING = TILE_HX * TILE_HY - TILE_X * TILE_Y;  // 84
+
+// Position h (0..83) of the ring around a tile, in tile-with-ring coordinates.
+__device__ inline void tile_ring_pos(int h, int& hx, int& hy) {
+  if (h < TILE_HX) {
+    hx = h;
+    hy = 0;
+  } else if (h < 2 * TILE_HX) {
+    hx = h - TILE_HX;
+    hy = TILE_HY - 1;
   } else {
-    psi = p.psi_solid;
-    c = drho = jx = jy = 0.0;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) d[i] = 0.0;
+    const int r = h - 2 * TILE_HX;
+    hy = 1 + (r >> 1);
+    hx = (r & 1) ? TILE_HX - 1 : 0;
   }
 }
 
+// psi of lattice position (x, y), at most one node outside the box: psi_solid
+// across a non-periodic edge or on a solid node, else the psi of the pulled
+// (wrapped) node.  Positions farther out (the ring of a tile that overhangs the
+// box) are no node's neighbour; they get psi_solid without a memory access.
+template <class S>
+__device__ inline double tile_psi_at(const StepParams& p, const S* __restrict__ f, const uint8_t* __restrict__ mask,
+                                     const double* __restrict__ wall_u, int x, int y) {
+  if (x < -1 || x > p.nx || y < -1 || y > p.ny) return p.psi_solid;
+  int xw, yw;
+  bool inside;
+  if (solid_at(p, mask, x, y, xw, yw, inside)) return p.psi_solid;
+  double d[9], c;
+  pull_node<S>(p, f, mask, wall_u, xw, yw, d, nullptr, c);
+  double drho, jx, jy;
+  node_sums<S>(d, c, drho, jx, jy);
+  bool bad;
+  return psi_of(p, p.rho_ref + drho, bad);
+}
+
+int tile_blocks(int nx, int ny) { return ((nx + TILE_X - 1) / TILE_X) * ((ny + TILE_Y - 1) / TILE_Y); }
+
 template <class S, bool REDUCE>
-__global__ __launch_bounds__(256) void fused_kernel(StepParams p, const S* __restrict__ f, S* __restrict__ fo,
-                                                    const uint8_t* __restrict__ mask,
-                                                    const double* __restrict__ wall_u, int n_strips, int seg_len,
-                                                    int n_segs, double* __restrict__ partials) {
-  const int lane = threadIdx.x % WAVE;
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-  if (wave >= n_strips * n_segs) return;  // whole wave exits together
-  const int strip = wave % n_strips;
-  const int seg = wave / n_strips;
-  const int x0 = strip * STRIP;
-  const int x = x0 - 1 + lane;
-  const int y0 = seg * seg_len;
-  const int y1 = min(y0 + seg_len, p.ny);
-  // a lane is a real column (or the periodic/wall column just outside) if x <= nx
-  const bool lane_in = (x <= p.nx);
-  const bool owner = (lane >= 1 && lane <= STRIP && x < p.nx);
-  const size_t plane = (size_t)p.nx * p.ny;
+__global__ __launch_bounds__(256) void tile_kernel(StepParams p, const S* __restrict__ f, S* __restrict__ fo,
+                                                   const uint8_t* __restrict__ mask,
+                                                   const double* __restrict__ wall_u, double* __restrict__ partials) {
+  __shared__ double lpsi[TILE_HY][TILE_HX];
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int x0 = blockIdx.x * TILE_X, y0 = blockIdx.y * TILE_Y;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool active = x < p.nx && y < p.ny;
+  const size_t k = active ? (size_t)y * p.nx + x : 0;
+  const bool fluid = active && !(mask && mask[k]);
+  double d[9], c = 0.0, drho = 0.0, jx = 0.0, jy = 0.0;
+  float cd[9];
+  double wall[2] = {0.0, 0.0};
+  bool bad = false;
+  double ps = p.psi_solid;
+  if (fluid) {
+    pull_node<S>(p, f, mask, wall_u, x, y, d, REDUCE ? wall : nullptr, c, sizeof(S) == 4 ? cd : nullptr);
+    node_sums<S>(d, c, drho, jx, jy);
+    ps = psi_of(p, p.rho_ref + drho, bad);
+  } else if (!active) {
+    // a tile position past the box's last column or row: the wrapped node, or
+    // beyond a wall
+    ps = tile_psi_at<S>(p, f, mask, wall_u, x, y);
+  }
+  lpsi[ty + 1][tx + 1] = ps;
+  const int tid = ty * TILE_X + tx;
+  if (tid < TILE_RING) {
+    int hx, hy;
+    tile_ring_pos(tid, hx, hy);
+    lpsi[hy][hx] = tile_psi_at<S>(p, f, mask, wall_u, x0 - 1 + hx, y0 - 1 + hy);
+  }
+  __syncthreads();
 
   double acc[RED_COUNT];
 #pragma unroll
   for (int q = 0; q < RED_COUNT; ++q) acc[q] = 0.0;
-
-  double dc[9], dn[9];
-  double cc, cn;
-  // float storage: offsets of the nodes that pull the current / next row's populations
-  float cdc[9], cdn[9];
-  double drc, jxc, jyc, drn, jxn, jyn;
-  double psm, psc, psn;
-  bool flc, fln, badc, badn;
-  double wallc[2] = {0.0, 0.0}, walln[2] = {0.0, 0.0};
-
-  // prologue: halo row y0-1 (psi only) and row y0
-  {
-    double dtmp[9], ct, a, b, c;
-    bool ftmp, btmp;
-    strip_row_pull<S>(p, f, mask, wall_u, x, y0 - 1, lane_in, dtmp, ct, nullptr, a, b, c, psm, ftmp, btmp, nullptr);
-  }
-  strip_row_pull<S>(p, f, mask, wall_u, x, y0, lane_in, dc, cc, sizeof(S) == 4 ? cdc : nullptr, drc, jxc, jyc, psc,
-                    flc, badc, REDUCE ? wallc : nullptr);
-
-  for (int y = y0; y < y1; ++y) {
-    walln[0] = walln[1] = 0.0;
-    strip_row_pull<S>(p, f, mask, wall_u, x, y + 1, lane_in, dn, cn, sizeof(S) == 4 ? cdn : nullptr, drn, jxn, jyn,
-                      psn, fln, badn,
-                      (REDUCE && y + 1 < y1) ? walln : nullptr);
-    // neighbours' psi through the wavefront (lanes 0 and 63 never collide)
-    double pW = shfl_up1(psc), pE = shfl_down1(psc);
-    double pSW = shfl_up1(psm), pSE = shfl_down1(psm);
-    double pNW = shfl_up1(psn), pNE = shfl_down1(psn);
-    if (owner && flc) {
-      double Sx, Sy;
-      stencil_sums(pE, psn, pW, psm, pNE, pNW, pSW, pSE, Sx, Sy);
-      NodeMacro mac = collide_node<S>(p, dc, cc, drc, jxc, jyc, psc, Sx, Sy);
-      const size_t k = (size_t)y * p.nx + x;
+  if (fluid) {
+    double Sx, Sy;
+    stencil_sums(lpsi[ty + 1][tx + 2], lpsi[ty + 2][tx + 1], lpsi[ty + 1][tx], lpsi[ty][tx + 1], lpsi[ty + 2][tx + 2],
+                 lpsi[ty + 2][tx], lpsi[ty][tx], lpsi[ty][tx + 2], Sx, Sy);
+    NodeMacro mac = collide_node<S>(p, d, c, drho, jx, jy, ps, Sx, Sy);
+    const size_t plane = (size_t)p.nx * p.ny;
 #pragma unroll
-      for (int i = 0; i < 9; ++i)
-        fo[(size_t)i * plane + k] = store_value<S>(dc[i], wgt(i), sizeof(S) == 4 ? (double)cdc[i] : 0.0);
-      if (REDUCE) {
-        acc[RED_WALLX] += wallc[0];
-        acc[RED_WALLY] += wallc[1];
-        accumulate_node(p, acc, p.rho_ref + drc, jxc, jyc, mac, badc);
-      }
-    }
-    // rotate the row pipeline
-    psm = psc;
-    psc = psn;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      dc[i] = dn[i];
-      cdc[i] = cdn[i];
-    }
-    cc = cn;
-    drc = drn;
-    jxc = jxn;
-    jyc = jyn;
-    flc = fln;
-    badc = badn;
-    wallc[0] = walln[0];
-    wallc[1] = walln[1];
-  }
-  if (REDUCE) {
-#pragma unroll
-    for (int q = 0; q < RED_COUNT; ++q) {
-      double v = wave_sum(acc[q]);
-      if (lane == 0) partials[(size_t)wave * RED_COUNT + q] = v;
+    for (int i = 0; i < 9; ++i)
+      fo[(size_t)i * plane + k] = store_value<S>(d[i], wgt(i), sizeof(S) == 4 ? (double)cd[i] : 0.0);
+    if (REDUCE) {
+      acc[RED_WALLX] += wall[0];
+      acc[RED_WALLY] += wall[1];
+      accumulate_node(p, acc, p.rho_ref + drho, jx, jy, mac, bad);
     }
   }
+  if (REDUCE) block_reduce_store(acc, partials, blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 // ------------------------------------------------------------------ fast strip kernel
@@ -1287,16 +1273,12 @@ hipError_t launch_step(const StepParams& p, const StepLaunch& L, hipStream_t st)
   } else if (L.fast && launch_fast62<S>(p, L, st)) {
     // launched: the 62-column strip kernel (double storage, widths not a multiple of 64)
   } else {
-    int n_strips, n_segs;
-    fused_shape(p.nx, p.ny, L.seg_len, false, &n_strips, &n_segs);
-    int waves = n_strips * n_segs;
-    int blocks = (waves + 3) / 4;
+    dim3 blk(TILE_X, TILE_Y);
+    dim3 grd((p.nx + TILE_X - 1) / TILE_X, (p.ny + TILE_Y - 1) / TILE_Y);
     if (L.reduce)
-      hipLaunchKernelGGL((fused_kernel<S, true>), dim3(blocks), dim3(256), 0, st, p, f, fo, L.mask, L.wall_u,
-                         n_strips, L.seg_len, n_segs, L.partials);
+      hipLaunchKernelGGL((tile_kernel<S, true>), grd, blk, 0, st, p, f, fo, L.mask, L.wall_u, L.partials);
     else
-      hipLaunchKernelGGL((fused_kernel<S, false>), dim3(blocks), dim3(256), 0, st, p, f, fo, L.mask, L.wall_u,
-                         n_strips, L.seg_len, n_segs, L.partials);
+      hipLaunchKernelGGL((tile_kernel<S, false>), grd, blk, 0, st, p, f, fo, L.mask, L.wall_u, L.partials);
   }
   return hipGetLastError();
 }

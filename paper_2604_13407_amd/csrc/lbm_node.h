@@ -195,11 +195,13 @@ __host__ __device__ inline void dest_refs(const StepParams& p, const S* __restri
 // 0 for double storage).  When `wall` is non-null, accumulates the momentum
 // handed to the walls.  When `cdst` is non-null (float storage), also
 // returns the offsets of the nodes that will pull this node's post-collision
-// populations (the node x + e_i is the source of direction opp(i)).
+// populations (the node x + e_i is the source of direction opp(i)).  When
+// `sbits` is non-null, bit i of it is set when x - e_i is solid or beyond a
+// wall.
 template <class S>
 __host__ __device__ inline void pull_node(const StepParams& p, const S* __restrict__ f, const uint8_t* __restrict__ mask,
                                           const double* __restrict__ wall_u, int x, int y, double d[9], double* wall,
-                                          double& c, float* cdst = nullptr) {
+                                          double& c, float* cdst = nullptr, unsigned* sbits = nullptr) {
   const size_t plane = (size_t)p.nx * p.ny;
   const size_t self = (size_t)y * p.nx + x;
   // every population gathered here was stored relative to this node's offset
@@ -216,16 +218,25 @@ __host__ __device__ inline void pull_node(const StepParams& p, const S* __restri
     sol[i] = solid_at(p, mask, x - ex(i), y - ey(i), xs, ys, ins[i]);
     ks[i] = (size_t)ys * p.nx + xs;
   }
+  if (sbits) {
+    unsigned b = 0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) b |= sol[i] ? (1u << i) : 0u;
+    *sbits = b;
+  }
+  // offsets of the pullers: every index is in the box (solid_at wraps even
+  // across a non-periodic edge), so the loads are unconditional
   double cd[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) cd[i] = 0.0;
   if constexpr (sizeof(S) == 4) {
-    if (cdst || wall_u) {
+    if (cdst) {
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         const int j = opp(i);
-        cd[i] = sol[j] ? c_self : ref_offset<S>(f, plane, ks[j]);
-        if (cdst) cdst[i] = (float)cd[i];
+        const double cj = ref_offset<S>(f, plane, ks[j]);
+        cd[i] = sol[j] ? c_self : cj;
+        cdst[i] = (float)cd[i];
       }
     }
   }
@@ -234,14 +245,20 @@ __host__ __device__ inline void pull_node(const StepParams& p, const S* __restri
   bool have_rho_w = false;
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
-    if (!sol[i]) {
-      d[i] = (double)f[(size_t)i * plane + ks[i]];
-    } else {
-      double v = (double)f[(size_t)opp(i) * plane + self];
+    // the pulled population, or the node's own opposite one across a wall
+    const size_t src = sol[i] ? (size_t)opp(i) * plane + self : (size_t)i * plane + ks[i];
+    double v = (double)f[src];
+    if (sol[i]) {
       double mw = 0.0;
       if (wall_u && ins[i]) {
         if (!have_rho_w) {
           // density of this node at the previous step: sum of its own fbar
+          if constexpr (sizeof(S) == 4) {
+            if (!cdst) {
+#pragma unroll
+              for (int q = 0; q < 9; ++q) cd[q] = sol[opp(q)] ? c_self : ref_offset<S>(f, plane, ks[opp(q)]);
+            }
+          }
           double s = 0.0;
 #pragma unroll
           for (int q = 0; q < 9; ++q) s += (double)f[(size_t)q * plane + self] + wgt(q) * cd[q];
@@ -252,7 +269,6 @@ __host__ __device__ inline void pull_node(const StepParams& p, const S* __restri
         mw = 6.0 * wgt(i) * rho_w * eu;
         v += mw;
       }
-      d[i] = v;
       if (wall) {
         // the wall received -(f_i + fbar_opp) e_i, with f_i = fbar_opp + mw
         double fi = v + wgt(i) * (p.rho_ref + c_self);
@@ -261,6 +277,7 @@ __host__ __device__ inline void pull_node(const StepParams& p, const S* __restri
         wall[1] -= ey(i) * both;
       }
     }
+    d[i] = v;
   }
 }
 
