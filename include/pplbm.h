@@ -180,9 +180,10 @@ int lbm_init_equilibrium(lbm_lattice* h, const double* rho0_dev, const double* u
  * LBM_ERR_EOS_DOMAIN or LBM_ERR_NONFINITE after the copy. */
 int lbm_step(lbm_lattice* h, int64_t n, int32_t reduce_every, lbm_reduction* out_host, int64_t n_out);
 
-/* Launch tuning of the fused kernels: rows each wavefront marches through
- * (4 <= rows <= 4096; 0 restores the default chosen from the lattice size and
- * precision).
+/* Launch tuning of the fused strip kernels (lattices without solid masks or
+ * moving walls): rows each wavefront marches through (4 <= rows <= 4096; 0
+ * restores the default chosen from the lattice size and precision).  The
+ * tile kernel of other lattices does not use it.
  * Results do not depend on it. */
 int lbm_set_rows_per_wave(lbm_lattice* h, int32_t rows);
 
