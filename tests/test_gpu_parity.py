@@ -312,7 +312,7 @@ def test_rows_per_wave_do_not_change_results(precision, make):
             assert a["mass"] == pytest.approx(b["mass"], rel=1e-14)
 
 
-@pytest.mark.parametrize("make", [droplet_small, droplet_aligned])
+@pytest.mark.parametrize("make", [droplet_small, droplet_aligned, annulus_small])
 def test_rereference_keeps_the_run(make):
     """Float storage: re-referencing every node to its current density changes the
     stored values but not the run beyond rounding (checked against the FP64 oracle
