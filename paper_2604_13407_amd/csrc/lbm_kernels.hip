@@ -388,7 +388,7 @@ __global__ __launch_bounds__(256) void tile_kernel(StepParams p, const S* __rest
 //
 // The strip kernel specialised for lattices whose only walls are the planes
 // across non-periodic axes (no mask, no moving walls) and whose population
-// arrays fit 32-bit byte offsets.  Same arithmetic as fused_kernel; what
+// arrays fit 32-bit byte offsets.  Same arithmetic as the tile kernel; what
 // differs is the data movement:
 //  * loads and stores are buffer instructions whose offset is the plane and
 //    row (uniform) plus a lane-constant column; halfway bounce-back is a
