@@ -278,6 +278,20 @@ __global__ void fields_kernel(StepParams p, const S* __restrict__ f, const uint8
   if (reduce) block_reduce_store(acc, partials, blockIdx.y * gridDim.x + blockIdx.x);
 }
 
+// The kernel's parameters, read again from the kernel-argument segment (the
+// StepParams argument is a kernel's first, at offset 0).  The strip march
+// calls it once per row and the tile kernel before its collision; the empty
+// asm hides that the address does not change, so the ~30 constants of the
+// step are scalar loads near their use instead of registers held across the
+// kernel; holding them exceeds the scalar register file, and the compiler's
+// spills cost a vector instruction per use.
+typedef const __attribute__((address_space(4))) StepParams* KernargParams;
+__device__ inline const StepParams& kernarg_params() {
+  KernargParams kp = (KernargParams)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(kp));
+  return *(const StepParams*)kp;
+}
+
 // ------------------------------------------------------------------ fused tile kernel
 //
 // The fused step for every lattice the strip kernels do not take (solid
@@ -363,6 +377,7 @@ __global__ __launch_bounds__(256) void tile_kernel(StepParams p, const S* __rest
   }
   __syncthreads();
 
+  const StepParams& pc = kernarg_params();
   double acc[RED_COUNT];
 #pragma unroll
   for (int q = 0; q < RED_COUNT; ++q) acc[q] = 0.0;
@@ -370,15 +385,15 @@ __global__ __launch_bounds__(256) void tile_kernel(StepParams p, const S* __rest
     double Sx, Sy;
     stencil_sums(lpsi[ty + 1][tx + 2], lpsi[ty + 2][tx + 1], lpsi[ty + 1][tx], lpsi[ty][tx + 1], lpsi[ty + 2][tx + 2],
                  lpsi[ty + 2][tx], lpsi[ty][tx], lpsi[ty][tx + 2], Sx, Sy);
-    NodeMacro mac = collide_node<S>(p, d, c, drho, jx, jy, ps, Sx, Sy);
-    const size_t plane = (size_t)p.nx * p.ny;
+    NodeMacro mac = collide_node<S>(pc, d, c, drho, jx, jy, ps, Sx, Sy);
+    const size_t plane = (size_t)pc.nx * pc.ny;
 #pragma unroll
     for (int i = 0; i < 9; ++i)
       fo[(size_t)i * plane + k] = store_value<S>(d[i], wgt(i), sizeof(S) == 4 ? (double)cd[i] : 0.0);
     if (REDUCE) {
       acc[RED_WALLX] += wall[0];
       acc[RED_WALLY] += wall[1];
-      accumulate_node(p, acc, p.rho_ref + drho, jx, jy, mac, bad);
+      accumulate_node(pc, acc, pc.rho_ref + drho, jx, jy, mac, bad);
     }
   }
   if (REDUCE) block_reduce_store(acc, partials, blockIdx.y * gridDim.x + blockIdx.x);
@@ -954,20 +969,6 @@ __device__ inline void arow_state(const StepParams& p, const AMarch& m, const AS
   bool badh;
   const double psh = psi_of(p, p.rho_ref + hr, badh);
   t.psih = (t.g.real && m.h.real) ? psh : p.psi_solid;
-}
-
-// The kernel's parameters, read again from the kernel-argument segment (the
-// StepParams argument is the kernel's first, at offset 0).  The march calls it
-// once per row, and the empty asm hides that the address does not change, so
-// the ~30 constants of the step are scalar loads near their use instead of
-// registers held across the whole march; holding them exceeds the scalar
-// register file, and the compiler's spills cost a vector instruction per
-// use.
-typedef const __attribute__((address_space(4))) StepParams* KernargParams;
-__device__ inline const StepParams& kernarg_params() {
-  KernargParams kp = (KernargParams)__builtin_amdgcn_kernarg_segment_ptr();
-  asm volatile("" : "+s"(kp));
-  return *(const StepParams*)kp;
 }
 
 // Collide and store row y (slot `s0`, state `t0`), with psi of rows y-1 (`tm`)
