@@ -849,7 +849,17 @@ struct AMarch {
   ColGeo c;   // the lane's column
   ColGeo h;   // lane 0: column x0-1, lane 63: column x0+64; real where that node exists
   int y1;
-  unsigned colB[9], colH[9];  // byte offsets of the pulled columns (interior strips)
+  unsigned colB[9];  // byte offsets of the pulled columns (interior strips)
+  // The columns beside the strip are pulled one population per lane: lane
+  // l <= 8 pulls population l of column x0-1, lane 63-i population i of
+  // column x0+64 (one load instruction per row).  Lane constants of that
+  // pull: the population's plane and source column (element offsets), the
+  // node's own opposite plane and column (bounce-back), its e_y, whether its
+  // source column lies beyond a wall, and whether the lane pulls at all.
+  unsigned hplane, hcol, hback;
+  int hey;
+  bool hwall, hon;
+  bool lane0;
   // float storage: the reference plane, and the column byte offset of the
   // halo column's reference (the lane's own where there is none)
   unsigned refbytes, href;
@@ -864,8 +874,8 @@ struct RefRow {
 
 template <class S>
 struct ASlot {
-  S raw[9];   // the lane's 9 pulled populations (stored values)
-  S rawh[9];  // lanes 0 and 63: those of the halo column
+  S raw[9];  // the lane's 9 pulled populations (stored values)
+  S rh;      // lanes 0-8 and 55-63: one population of a column beside the strip
   RefRow r;   // float storage: the reference offsets of this row
 };
 
@@ -888,14 +898,18 @@ __device__ inline void aissue_row(const StepParams& p, const AMarch& m, int y, b
       const unsigned row = eyi == 1 ? g.bot : (eyi == -1 ? g.top : g.own);
       const unsigned rb = ((unsigned)i * m.N + row) * (unsigned)sizeof(S);
       sl.raw[i] = BufIO<S>::load(in, m.colB[i], rb);
-      sl.rawh[i] = BufIO<S>::load(in, m.colH[i], rb);
     }
   } else {
-    unsigned off[9], offh[9];
+    unsigned off[9];
     pull_offsets<S>(g, m.c, m.N, m.bytes, off);
-    pull_offsets<S>(g, m.h, m.N, m.bytes, offh);
     load_row<S>(in, off, sl.raw);
-    load_row<S>(in, offh, sl.rawh);
+  }
+  {
+    // the columns beside the strip, one population per lane
+    const unsigned row = m.hey == 1 ? g.bot : (m.hey == -1 ? g.top : g.own);
+    const bool wall = !INTERIOR && (m.hwall || (m.hey == 1 && g.wall_b) || (m.hey == -1 && g.wall_t));
+    const unsigned e = wall ? m.hback + g.own : m.hplane + row + m.hcol;
+    sl.rh = BufIO<S>::load(in, (m.hon && g.real) ? e * (unsigned)sizeof(S) : m.bytes);
   }
   if constexpr (sizeof(S) == 4) {
     // every population pulled into this row was stored relative to the
@@ -944,14 +958,40 @@ __device__ inline void dest_refs_row(const AMarch& m, const RowGeo& g, const Ref
   }
 }
 
+// DPP move of a double within rows of 16 lanes (CTRL 0x100 + k: lane l
+// receives lane l+k's v; 0x110 + k: lane l-k's); lanes without a source lane
+// keep their own v.
+template <int CTRL>
+__device__ inline double row_dpp(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  int lo = (int)(unsigned)b, hi = (int)(unsigned)(b >> 32);
+  lo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Sum of the 9 populations of the columns beside the strip, pulled one per
+// lane, in node_sums' order d0 + ((d1 + d3) + (d2 + d4)) + ((d5 + d7) + (d6 + d8)),
+// so that psi there is bitwise the one the column's own strip computes:
+// column x0-1 into lane 0 (lane l holds d_l), column x0+64 into lane 63
+// (lane 63-i holds d_i).
+__device__ inline double halo_sum(double v, bool lane0) {
+  const double a1 = v + row_dpp<0x102>(v);     // lane 1: d1+d3, 2: d2+d4, 5: d5+d7, 6: d6+d8
+  const double a2 = a1 + row_dpp<0x101>(a1);   // lane 1: S4, lane 5: S8
+  const double a3 = v + row_dpp<0x101>(a2);    // lane 0: d0 + S4
+  const double a4 = a3 + row_dpp<0x105>(a2);   // lane 0: (d0 + S4) + S8
+  const double b1 = v + row_dpp<0x112>(v);     // lane 62: d1+d3, 61: d2+d4, 58: d5+d7, 57: d6+d8
+  const double b2 = b1 + row_dpp<0x111>(b1);   // lane 62: S4, lane 58: S8
+  const double b3 = v + row_dpp<0x111>(b2);    // lane 63: d0 + S4
+  const double b4 = b3 + row_dpp<0x115>(b2);   // lane 63: (d0 + S4) + S8
+  return lane0 ? a4 : b4;
+}
+
 template <class S>
 __device__ inline void arow_state(const StepParams& p, const AMarch& m, const ASlot<S>& sl, ARow& t) {
-  double d[9], dh[9];
+  double d[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    d[i] = (double)sl.raw[i];
-    dh[i] = (double)sl.rawh[i];
-  }
+  for (int i = 0; i < 9; ++i) d[i] = (double)sl.raw[i];
   double cm = 0.0, ch = 0.0;
   if constexpr (sizeof(S) == 4) {
     cm = (double)sl.r.m;
@@ -964,8 +1004,8 @@ __device__ inline void arow_state(const StepParams& p, const AMarch& m, const AS
   t.psi = t.g.real ? ps : p.psi_solid;
   t.bad = t.g.real && bad;
   // the halo column's density in the same arithmetic as its own strip uses
-  double hr, hx, hy;
-  node_sums<S>(dh, ch, hr, hx, hy);
+  double hr = halo_sum((double)sl.rh, m.lane0);
+  if constexpr (sizeof(S) == 4) hr += ch;
   bool badh;
   const double psh = psi_of(p, p.rho_ref + hr, badh);
   t.psih = (t.g.real && m.h.real) ? psh : p.psi_solid;
@@ -1138,8 +1178,21 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
   for (int i = 0; i < 9; ++i) {
     const int exi = ex(i);
     m.colB[i] = (exi == 1 ? m.c.left : (exi == -1 ? m.c.right : m.c.own)) * (unsigned)sizeof(S);
-    m.colH[i] = hl ? (exi == 1 ? m.h.left : (exi == -1 ? m.h.right : m.h.own)) * (unsigned)sizeof(S) : m.colB[i];
   }
+  {
+    // the columns beside the strip, one population per lane
+    const bool left = lane <= 8, right = lane >= WAVE - 9;
+    const int hi = left ? lane : (right ? WAVE - 1 - lane : 0);
+    const ColGeo hg = col_geo(p, left ? x0 - 1 : x0 + WAVE, left || right);
+    const int exi = ex(hi);
+    m.hplane = (unsigned)hi * m.N;
+    m.hcol = exi == 1 ? hg.left : (exi == -1 ? hg.right : hg.own);
+    m.hback = (unsigned)opp(hi) * m.N + hg.own;
+    m.hey = ey(hi);
+    m.hwall = (exi == 1 && hg.wall_l) || (exi == -1 && hg.wall_r);
+    m.hon = (left || right) && hg.real;
+  }
+  m.lane0 = lane == 0;
   // the reference plane follows the 9 population planes (float storage)
   m.refbytes = m.N * 2u;
   m.href = (m.h.real ? m.h.own : m.c.own) * 2u;
