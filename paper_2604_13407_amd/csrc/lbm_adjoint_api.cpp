@@ -144,8 +144,11 @@ int lbm_adjoint_forward(lbm_lattice* h, const lbm_adjoint_cfg* a, const double* 
   const int64_t N = a->n_steps, K = a->checkpoint_every;
   const int64_t first_logged = (a->loss == LBM_LOSS_DRAG) ? N - a->window + 1 : N;
 
-  hipError_t e = fp64 ? pplbm::launch_init<double>(h->prm, rho0, nullptr, nullptr, h->buf.mask, h->buf.f_a, h->buf.f_b, h->stream)
-                      : pplbm::launch_init<float>(h->prm, rho0, nullptr, nullptr, h->buf.mask, h->buf.f_a, h->buf.f_b, h->stream);
+  const uint8_t* mask = h->buf.mask;
+  hipError_t e = fp64 ? pplbm::launch_init<double>(h->prm, rho0, nullptr, nullptr, mask, h->buf.f_a, h->buf.f_b,
+                                                   h->stream)
+                      : pplbm::launch_init<float>(h->prm, rho0, nullptr, nullptr, mask, h->buf.f_a, h->buf.f_b,
+                                                  h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "init launch");
   h->cur = 0;
   h->steps = 0;

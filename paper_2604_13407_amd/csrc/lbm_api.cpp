@@ -407,8 +407,10 @@ int lbm_init_equilibrium(lbm_lattice* h, const double* rho0, const double* ux0, 
   if (!h) return LBM_ERR_INVALID_ARG;
   if (!rho0) return fail(h, LBM_ERR_INVALID_ARG, "rho0 is NULL");
   hipError_t e = (h->cfg.precision == LBM_FP64)
-                     ? pplbm::launch_init<double>(h->prm, rho0, ux0, uy0, h->buf.mask, h->buf.f_a, h->buf.f_b, h->stream)
-                     : pplbm::launch_init<float>(h->prm, rho0, ux0, uy0, h->buf.mask, h->buf.f_a, h->buf.f_b, h->stream);
+                     ? pplbm::launch_init<double>(h->prm, rho0, ux0, uy0, h->buf.mask, h->buf.f_a, h->buf.f_b,
+                                                  h->stream)
+                     : pplbm::launch_init<float>(h->prm, rho0, ux0, uy0, h->buf.mask, h->buf.f_a, h->buf.f_b,
+                                                 h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "init launch");
   h->cur = 0;
   h->steps = 0;
