@@ -12,8 +12,12 @@
  * Conventions
  *  - Lattice units dx = dt = c = 1, c_s^2 = 1/3.  D2Q9 velocities
  *    e0..e8 = (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1).
- *  - Arrays are row-major with x fastest.  Populations are structure-of-arrays
- *    f[i][y][x]; scalar fields are [y][x]; vector fields [2][y][x].
+ *  - Arrays are row-major with x fastest.  Scalar fields are [y][x]; vector
+ *    fields [2][y][x].  A population array holds rows of planes,
+ *    f[y][p][x]: row y is P runs of nx elements, the row's values of the 9
+ *    populations (p = i) and, for LBM_FP32_DEV, a tenth run with the row's
+ *    reference offsets (below).  Population i of node (x, y) is element
+ *    (y * P + i) * nx + x, P = 9 (LBM_FP64) or 10 (LBM_FP32_DEV).
  *  - The stored state is the post-collision field.  A step streams then
  *    collides.  "Macroscopic fields of the current state" are the pre-collision
  *    fields the next step would use.
@@ -21,9 +25,9 @@
  *    each post-collision population relative to the reference density of the
  *    node that will pull it: s_i(x) = f_i(x) - w_i * rhat(x + e_i) (rhat(x)
  *    when x + e_i is solid or beyond a wall), with rhat = rho_ref + c and the
- *    offsets c kept as 16-bit floats in the first half of a tenth plane of the
- *    population array (set from the initial density; see lbm_rereference;
- *    the plane's second half is zero).  The stored deviations stay small in
+ *    offsets c kept as 16-bit floats in the first half of each row's tenth
+ *    run (16-bit element 2 (10 y + 9) nx + x; set from the initial density,
+ *    see lbm_rereference; the run's second half is zero).  The stored deviations stay small in
  *    liquid and vapour alike, so their rounding stays small where a uniform
  *    reference would not.  Both precisions compute the step in double (each
  *    population is rounded once when stored) and reduce in double.
@@ -49,7 +53,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 1
+#define LBM_ABI_VERSION 2
 
 enum lbm_status {
   LBM_OK = 0,
@@ -83,8 +87,8 @@ typedef struct lbm_config {
 
 /* Caller-owned device buffers. */
 typedef struct lbm_buffers {
-  void* f_a;               /* population array of lbm_state_bytes: [9][ny][nx] double, or
-                              [10][ny][nx] float (9 planes + the reference plane) */
+  void* f_a;               /* population array of lbm_state_bytes: [ny][9][nx] double, or
+                              [ny][10][nx] float (9 populations + the reference offsets) */
   void* f_b;               /* second population array of the same size (ping-pong) */
   void* workspace;         /* lbm_workspace_bytes() bytes, 256-byte aligned */
   const uint8_t* mask;     /* [ny][nx], 1 = solid node, 0 = fluid; NULL = no solid nodes inside */
@@ -113,7 +117,7 @@ typedef struct lbm_lattice lbm_lattice;
 int lbm_abi_version(void);
 
 /* Bytes of one population array (f_a or f_b) for this configuration: 9 planes
- * of double, or 10 planes of float (the populations and the reference plane). */
+ * of double, or 10 planes of float (the populations and the reference offsets). */
 int lbm_state_bytes(const lbm_config* cfg, size_t* bytes);
 
 /* Bytes of the workspace (reduction partials, reduction log, two-pass
@@ -206,7 +210,7 @@ int lbm_reduce(lbm_lattice* h, lbm_reduction* out_host);
 int lbm_state_ptr(const lbm_lattice* h, void** f_dev);
 
 /* Checkpoint / resume: copy the current state (populations, and for
- * LBM_FP32_DEV the reference plane) to / from a caller buffer of
+ * LBM_FP32_DEV the reference offsets) to / from a caller buffer of
  * lbm_state_bytes (device, enqueued device-to-device copy).  lbm_set_state
  * also sets the step counter. */
 int lbm_get_state(lbm_lattice* h, void* dst_dev);

@@ -43,8 +43,8 @@ int hip_fail(lbm_lattice* h, hipError_t e, const char* what) {
 // The specialised strip kernel handles lattices without a mask or moving walls
 // whose population arrays fit 32-bit byte offsets.
 bool fast_path(const lbm_lattice* h) {
-  // 32-bit byte offsets into the 9 population planes
-  double bytes = 9.0 * (double)h->cfg.nx * (double)h->cfg.ny * (double)elem_size(&h->cfg);
+  // 32-bit byte offsets into the population array
+  double bytes = (double)state_bytes_of(&h->cfg);
   return h->cfg.kernel == LBM_KERNEL_FUSED && !h->buf.mask && !h->buf.wall_u && bytes < 4294967040.0;
 }
 

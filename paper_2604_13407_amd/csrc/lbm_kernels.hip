@@ -46,7 +46,6 @@ __global__ void init_kernel(StepParams p, const double* __restrict__ rho0, const
   int y = blockIdx.y * blockDim.y + threadIdx.y;
   if (x >= p.nx || y >= p.ny) return;
   size_t k = (size_t)y * p.nx + x;
-  size_t plane = (size_t)p.nx * p.ny;
   double r = rho0[k];
   double u = ux0 ? ux0[k] : 0.0;
   double v = uy0 ? uy0[k] : 0.0;
@@ -60,11 +59,12 @@ __global__ void init_kernel(StepParams p, const double* __restrict__ rho0, const
   for (int i = 0; i < 9; ++i) cd[i] = 0.0;
   if constexpr (sizeof(S) == 4) {
     const RefT cf = (RefT)(r - p.rho_ref);
-    ref_plane(fa, plane)[k] = cf;
-    ref_plane(fb, plane)[k] = cf;
-    // the plane's unused second half is zero, so the whole state is defined
-    ref_plane(fa, plane)[plane + k] = (RefT)0;
-    ref_plane(fb, plane)[plane + k] = (RefT)0;
+    const size_t rk = ref_at(p.nx, y, x);
+    ref_base(fa)[rk] = cf;
+    ref_base(fb)[rk] = cf;
+    // the run's unused second half is zero, so the whole state is defined
+    ref_base(fa)[rk + p.nx] = (RefT)0;
+    ref_base(fb)[rk + p.nx] = (RefT)0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       int xd, yd;
@@ -78,41 +78,40 @@ __global__ void init_kernel(StepParams p, const double* __restrict__ rho0, const
     double eu = ex(i) * u + ey(i) * v;
     // f_eq - w (rho_ref + c) = w [(rho - rho_ref - c) + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u^2)]
     double dv = wgt(i) * ((r - p.rho_ref - cd[i]) + r * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq));
-    fa[(size_t)i * plane + k] = (S)dv;
-    fb[(size_t)i * plane + k] = (S)dv;
+    fa[pop_at<S>(p.nx, y, i, x)] = (S)dv;
+    fb[pop_at<S>(p.nx, y, i, x)] = (S)dv;
   }
 }
 
 // Re-reference (float storage), three passes over the current array `fa`:
 // the new offset of every fluid node (the density of its current
-// post-collision populations) goes to the reference plane of `fb`; then every
-// stored population moves from its puller's old offset to the new one, in
-// both arrays; then the new plane is copied into `fa`.  The state is
+// post-collision populations) goes to the reference offsets of `fb`; then
+// every stored population moves from its puller's old offset to the new one,
+// in both arrays; then the new offsets are copied into `fa`.  The state is
 // unchanged up to one rounding per population.
 __global__ void reref_new_kernel(StepParams p, const float* __restrict__ fa, float* __restrict__ fb,
                                  const uint8_t* mask) {
   int x = blockIdx.x * blockDim.x + threadIdx.x;
   int y = blockIdx.y * blockDim.y + threadIdx.y;
   if (x >= p.nx || y >= p.ny) return;
-  const size_t plane = (size_t)p.nx * p.ny;
   const size_t k = (size_t)y * p.nx + x;
+  const size_t rk = ref_at(p.nx, y, x);
   if (mask && mask[k]) {
-    ref_plane(fb, plane)[k] = ref_plane(fa, plane)[k];
+    ref_base(fb)[rk] = ref_base(fa)[rk];
     return;
   }
   double cd[9];
   dest_refs<float>(p, fa, mask, x, y, cd);
   double s = 0.0;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) s += (double)fa[(size_t)i * plane + k] + wgt(i) * cd[i];
-  ref_plane(fb, plane)[k] = (RefT)s;
+  for (int i = 0; i < 9; ++i) s += (double)fa[pop_at<float>(p.nx, y, i, x)] + wgt(i) * cd[i];
+  ref_base(fb)[rk] = (RefT)s;
 }
 
 __global__ void reref_shift_kernel(StepParams p, float* __restrict__ fa, float* __restrict__ fb, const uint8_t* mask) {
   int x = blockIdx.x * blockDim.x + threadIdx.x;
   int y = blockIdx.y * blockDim.y + threadIdx.y;
   if (x >= p.nx || y >= p.ny) return;
-  const size_t plane = (size_t)p.nx * p.ny;
   const size_t k = (size_t)y * p.nx + x;
   if (mask && mask[k]) return;
   double co[9], cn[9];
@@ -120,9 +119,10 @@ __global__ void reref_shift_kernel(StepParams p, float* __restrict__ fa, float* 
   dest_refs<float>(p, fb, mask, x, y, cn);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    const float v = (float)((double)fa[(size_t)i * plane + k] + wgt(i) * (co[i] - cn[i]));
-    fa[(size_t)i * plane + k] = v;
-    fb[(size_t)i * plane + k] = v;
+    const size_t e = pop_at<float>(p.nx, y, i, x);
+    const float v = (float)((double)fa[e] + wgt(i) * (co[i] - cn[i]));
+    fa[e] = v;
+    fb[e] = v;
   }
 }
 
@@ -130,9 +130,8 @@ __global__ void reref_copy_kernel(StepParams p, float* __restrict__ fa, const fl
   int x = blockIdx.x * blockDim.x + threadIdx.x;
   int y = blockIdx.y * blockDim.y + threadIdx.y;
   if (x >= p.nx || y >= p.ny) return;
-  const size_t plane = (size_t)p.nx * p.ny;
-  const size_t k = (size_t)y * p.nx + x;
-  ref_plane(fa, plane)[k] = ref_plane(fb, plane)[k];
+  const size_t rk = ref_at(p.nx, y, x);
+  ref_base(fa)[rk] = ref_base(fb)[rk];
 }
 
 // ------------------------------------------------------------------ two-pass: psi
@@ -210,10 +209,9 @@ __global__ void collide_kernel(StepParams p, const S* __restrict__ f, S* __restr
                  psi_at(p, psi, mask, x, y - 1), psi_at(p, psi, mask, x + 1, y + 1), psi_at(p, psi, mask, x - 1, y + 1),
                  psi_at(p, psi, mask, x - 1, y - 1), psi_at(p, psi, mask, x + 1, y - 1), Sx, Sy);
     NodeMacro mac = collide_node<S>(p, d, c, drho, jx, jy, psi[k], Sx, Sy);
-    const size_t plane = (size_t)p.nx * p.ny;
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-      fo[(size_t)i * plane + k] = store_value<S>(d[i], wgt(i), sizeof(S) == 4 ? (double)cd[i] : 0.0);
+      fo[pop_at<S>(p.nx, y, i, x)] = store_value<S>(d[i], wgt(i), sizeof(S) == 4 ? (double)cd[i] : 0.0);
     if (REDUCE) {
       bool bad;
       double rho = p.rho_ref + drho;
@@ -386,10 +384,9 @@ __global__ __launch_bounds__(256) void tile_kernel(StepParams p, const S* __rest
     stencil_sums(lpsi[ty + 1][tx + 2], lpsi[ty + 2][tx + 1], lpsi[ty + 1][tx], lpsi[ty][tx + 1], lpsi[ty + 2][tx + 2],
                  lpsi[ty + 2][tx], lpsi[ty][tx], lpsi[ty][tx + 2], Sx, Sy);
     NodeMacro mac = collide_node<S>(pc, d, c, drho, jx, jy, ps, Sx, Sy);
-    const size_t plane = (size_t)pc.nx * pc.ny;
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-      fo[(size_t)i * plane + k] = store_value<S>(d[i], wgt(i), sizeof(S) == 4 ? (double)cd[i] : 0.0);
+      fo[pop_at<S>(pc.nx, y, i, x)] = store_value<S>(d[i], wgt(i), sizeof(S) == 4 ? (double)cd[i] : 0.0);
     if (REDUCE) {
       acc[RED_WALLX] += wall[0];
       acc[RED_WALLY] += wall[1];
@@ -531,8 +528,9 @@ struct ColGeo {
 // Byte offsets of the 9 pulled populations of node (row g, column c);
 // `oob` (>= the buffer size) for a node that does not exist.
 template <class S>
-__device__ inline void pull_offsets(const RowGeo& g, const ColGeo& c, unsigned N, unsigned oob, unsigned off[9]) {
-  const unsigned own = g.own + c.own;
+__device__ inline void pull_offsets(const RowGeo& g, const ColGeo& c, unsigned nx, unsigned oob, unsigned off[9]) {
+  constexpr unsigned P = state_planes<S>();
+  const unsigned own = P * g.own + c.own;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const int exi = ex(i), eyi = ey(i);
@@ -540,7 +538,7 @@ __device__ inline void pull_offsets(const RowGeo& g, const ColGeo& c, unsigned N
     const unsigned col = exi == 1 ? c.left : (exi == -1 ? c.right : c.own);
     const bool wall = (eyi == 1 && g.wall_b) || (eyi == -1 && g.wall_t) || (exi == 1 && c.wall_l) ||
                       (exi == -1 && c.wall_r);
-    const unsigned e = wall ? (unsigned)opp(i) * N + own : (unsigned)i * N + row + col;
+    const unsigned e = wall ? (unsigned)opp(i) * nx + own : P * row + (unsigned)i * nx + col;
     off[i] = (g.real && c.real) ? e * (unsigned)sizeof(S) : oob;
   }
 }
@@ -575,7 +573,7 @@ __device__ inline void row_state(const StepParams& p, const S raw[9], bool exist
 // March state of one wavefront.
 struct March {
   __amdgpu_buffer_rsrc_t in, out;
-  unsigned N, bytes;
+  unsigned N, nx, bytes;
   ColGeo c;
   bool owner;
   int y1;
@@ -591,7 +589,7 @@ __device__ inline void pull_offsets_interior(const March& m, const RowGeo& g, un
   for (int i = 0; i < 9; ++i) {
     const int eyi = ey(i);
     const unsigned row = eyi == 1 ? g.bot : (eyi == -1 ? g.top : g.own);
-    off[i] = ((unsigned)i * m.N + row) * (unsigned)sizeof(S) + m.colB[i];
+    off[i] = (state_planes<S>() * row + (unsigned)i * m.nx) * (unsigned)sizeof(S) + m.colB[i];
   }
 }
 
@@ -608,7 +606,7 @@ __device__ inline void issue_row(const StepParams& p, const March& m, int y, boo
   if (INTERIOR)
     pull_offsets_interior<S>(m, g, off);
   else
-    pull_offsets<S>(g, m.c, m.N, m.bytes, off);
+    pull_offsets<S>(g, m.c, m.nx, m.bytes, off);
 #pragma unroll
   for (int i = 0; i < 9; ++i) off[i] = live ? off[i] : m.bytes;
   load_row<S>(m.in, off, raw);
@@ -636,7 +634,9 @@ __device__ inline void march_row(const StepParams& p, const March& m, int y, con
   const unsigned k = t0.g.own + m.c.own;
 #pragma unroll
   for (int i = 0; i < 9; ++i)
-    BufIO<S>::store((S)d[i], m.out, store ? ((unsigned)i * m.N + k) * (unsigned)sizeof(S) : m.bytes);
+    BufIO<S>::store((S)d[i], m.out,
+                    store ? (state_planes<S>() * t0.g.own + (unsigned)i * m.nx + m.c.own) * (unsigned)sizeof(S)
+                          : m.bytes);
   if (REDUCE && store) {
     if (!INTERIOR) {
       // bounce-back links: the wall received -(f_i + fbar_opp) e_i = -2 f_i e_i
@@ -680,7 +680,9 @@ __device__ inline void march_row4(const StepParams& p, const March& m, int y, co
   const unsigned k = t0.g.own + m.c.own;
 #pragma unroll
   for (int i = 0; i < 9; ++i)
-    BufIO<S>::store((S)d[i], m.out, store ? ((unsigned)i * m.N + k) * (unsigned)sizeof(S) : m.bytes);
+    BufIO<S>::store((S)d[i], m.out,
+                    store ? (state_planes<S>() * t0.g.own + (unsigned)i * m.nx + m.c.own) * (unsigned)sizeof(S)
+                          : m.bytes);
   if (REDUCE && store) {
     if (!INTERIOR) {
       double wx = 0.0, wy = 0.0;
@@ -762,7 +764,8 @@ __global__ __launch_bounds__(256) void fast_kernel(StepParams p, const S* __rest
   const int nx = p.nx;
   March m;
   m.N = (unsigned)nx * (unsigned)p.ny;
-  m.bytes = 9u * m.N * (unsigned)sizeof(S);
+  m.nx = (unsigned)nx;
+  m.bytes = (unsigned)state_planes<S>() * m.N * (unsigned)sizeof(S);
   m.in = __builtin_amdgcn_make_buffer_rsrc((void*)f, (short)0, (int)m.bytes, 0x00020000);
   m.out = __builtin_amdgcn_make_buffer_rsrc((void*)fo, (short)0, (int)m.bytes, 0x00020000);
 
@@ -845,7 +848,7 @@ __global__ __launch_bounds__(256) void fast_kernel(StepParams p, const S* __rest
 struct AMarch {
   const void* f;
   void* fo;
-  unsigned N, bytes;
+  unsigned N, nx, bytes;  // nodes, lattice width, bytes of the population array
   ColGeo c;   // the lane's column
   ColGeo h;   // lane 0: column x0-1, lane 63: column x0+64; real where that node exists
   int y1;
@@ -860,9 +863,9 @@ struct AMarch {
   int hey;
   bool hwall, hon;
   bool lane0;
-  // float storage: the reference plane, and the column byte offset of the
-  // halo column's reference (the lane's own where there is none)
-  unsigned refbytes, href;
+  // float storage: the column byte offset of the halo column's reference
+  // (the lane's own where there is none)
+  unsigned href;
   double* traj;  // replay: rho - rho_ref, j_x, j_y, psi of every stored node, [4][ny][nx]
 };
 
@@ -896,28 +899,30 @@ __device__ inline void aissue_row(const StepParams& p, const AMarch& m, int y, b
     for (int i = 0; i < 9; ++i) {
       const int eyi = ey(i);
       const unsigned row = eyi == 1 ? g.bot : (eyi == -1 ? g.top : g.own);
-      const unsigned rb = ((unsigned)i * m.N + row) * (unsigned)sizeof(S);
+      const unsigned rb = (state_planes<S>() * row + (unsigned)i * m.nx) * (unsigned)sizeof(S);
       sl.raw[i] = BufIO<S>::load(in, m.colB[i], rb);
     }
   } else {
     unsigned off[9];
-    pull_offsets<S>(g, m.c, m.N, m.bytes, off);
+    pull_offsets<S>(g, m.c, m.nx, m.bytes, off);
     load_row<S>(in, off, sl.raw);
   }
   {
     // the columns beside the strip, one population per lane
     const unsigned row = m.hey == 1 ? g.bot : (m.hey == -1 ? g.top : g.own);
     const bool wall = !INTERIOR && (m.hwall || (m.hey == 1 && g.wall_b) || (m.hey == -1 && g.wall_t));
-    const unsigned e = wall ? m.hback + g.own : m.hplane + row + m.hcol;
+    const unsigned e =
+        wall ? state_planes<S>() * g.own + m.hback : state_planes<S>() * row + m.hplane + m.hcol;
     sl.rh = BufIO<S>::load(in, (m.hon && g.real) ? e * (unsigned)sizeof(S) : m.bytes);
   }
   if constexpr (sizeof(S) == 4) {
     // every population pulled into this row was stored relative to the
     // puller's own offset: one offset per node
-    const __amdgpu_buffer_rsrc_t rf =
-        buf_rsrc((const float*)m.f + (size_t)9 * m.N, (live && g.real) ? m.refbytes : 0u);
-    sl.r.m = load_ref16(rf, m.c.own * 2u, g.own * 2u);
-    sl.r.h = load_ref16(rf, m.href, g.own * 2u);
+    // (the row's tenth run, from byte 4 (10 y + 9) nx)
+    const __amdgpu_buffer_rsrc_t rf = buf_rsrc(m.f, (live && g.real) ? m.bytes : 0u);
+    const unsigned rrow = 4u * (10u * g.own + 9u * m.nx);
+    sl.r.m = load_ref16(rf, m.c.own * 2u, rrow);
+    sl.r.h = load_ref16(rf, m.href, rrow);
   }
 }
 
@@ -1051,7 +1056,7 @@ __device__ inline void amarch_row(const AMarch& m, int y, const ASlot<S>& s0, co
 #pragma unroll
   for (int i = 0; i < 9; ++i)
     BufIO<S>::store(store_value<S>(d[i], wgt(i), (double)cd[i]), out, m.c.own * (unsigned)sizeof(S),
-                    ((unsigned)i * m.N + t0.g.own) * (unsigned)sizeof(S));
+                    (state_planes<S>() * t0.g.own + (unsigned)i * m.nx) * (unsigned)sizeof(S));
   if (TRAJ) {
     // the replayed step's pulled-state quantities, as the adjoint reads them
     const __amdgpu_buffer_rsrc_t tr = buf_rsrc(m.traj, store ? 4u * m.N * 8u : 0u);
@@ -1167,7 +1172,8 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
 
   AMarch m;
   m.N = (unsigned)p.nx * (unsigned)p.ny;
-  m.bytes = 9u * m.N * (unsigned)sizeof(S);
+  m.nx = (unsigned)p.nx;
+  m.bytes = (unsigned)state_planes<S>() * m.N * (unsigned)sizeof(S);
   m.f = f;
   m.fo = fo;
   const int x0 = strip * WAVE;
@@ -1185,16 +1191,16 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
     const int hi = left ? lane : (right ? WAVE - 1 - lane : 0);
     const ColGeo hg = col_geo(p, left ? x0 - 1 : x0 + WAVE, left || right);
     const int exi = ex(hi);
-    m.hplane = (unsigned)hi * m.N;
+    m.hplane = (unsigned)hi * m.nx;
     m.hcol = exi == 1 ? hg.left : (exi == -1 ? hg.right : hg.own);
-    m.hback = (unsigned)opp(hi) * m.N + hg.own;
+    m.hback = (unsigned)opp(hi) * m.nx + hg.own;
     m.hey = ey(hi);
     m.hwall = (exi == 1 && hg.wall_l) || (exi == -1 && hg.wall_r);
     m.hon = (left || right) && hg.real;
   }
   m.lane0 = lane == 0;
-  // the reference plane follows the 9 population planes (float storage)
-  m.refbytes = m.N * 2u;
+  // float storage: byte offset within a row's reference run of the halo
+  // column's offset (the lane's own where there is none)
   m.href = (m.h.real ? m.h.own : m.c.own) * 2u;
   m.traj = traj;
   const int y0 = seg * seg_len;

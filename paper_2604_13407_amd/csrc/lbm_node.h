@@ -125,31 +125,48 @@ __host__ __device__ inline bool solid_at(const StepParams& p, const uint8_t* __r
   return mask ? (mask[(size_t)y * p.nx + x] != 0) : false;
 }
 
-// Planes of a population array: 9 populations, plus the reference plane for
-// float storage, whose first half holds every node's offset c as a 16-bit
-// float (any representable c serves as a reference; 11 significant bits keep
-// the stored deviations small, and the plane costs 2 bytes per node to read).
+// Layout of a population array: rows of planes.  Row y holds P runs of nx
+// elements, P = state_planes<S>(): the row's values of the 9 populations
+// (f[y][i][x]: population i of node (x, y) is element (y P + i) nx + x), and
+// for float storage a tenth run whose first half holds the row's reference
+// offsets c as 16-bit floats (second half zero; any representable c serves as
+// a reference, 11 significant bits keep the stored deviations small, and the
+// offsets cost 2 bytes per node to read).  A wavefront pulling one row thus
+// reads the 9 populations from three neighbouring P-run blocks instead of 9
+// planes a whole lattice apart (measured: 5% faster for float storage).
 template <class S>
 __host__ __device__ constexpr int state_planes() {
   return sizeof(S) == 4 ? 10 : 9;
 }
 
+// Element index of population i of node (x, y).
+template <class S>
+__host__ __device__ inline size_t pop_at(int nx, int y, int i, int x) {
+  return ((size_t)y * state_planes<S>() + (size_t)i) * (size_t)nx + (size_t)x;
+}
+
 typedef _Float16 RefT;
 
-template <class S>
-__host__ __device__ inline RefT* ref_plane(S* f, size_t plane) {
-  return (RefT*)(f + 9 * plane);
-}
-template <class S>
-__host__ __device__ inline const RefT* ref_plane(const S* f, size_t plane) {
-  return (const RefT*)(f + 9 * plane);
+// Index, in 16-bit units of a float population array, of node (x, y)'s
+// reference offset.
+__host__ __device__ inline size_t ref_at(int nx, int y, int x) {
+  return 2 * ((size_t)y * 10 + 9) * (size_t)nx + (size_t)x;
 }
 
-// The reference offset c(k) of node k (0 for double storage).
 template <class S>
-__host__ __device__ inline double ref_offset(const S* __restrict__ f, size_t plane, size_t k) {
+__host__ __device__ inline RefT* ref_base(S* f) {
+  return (RefT*)f;
+}
+template <class S>
+__host__ __device__ inline const RefT* ref_base(const S* f) {
+  return (const RefT*)f;
+}
+
+// The reference offset c of node (x, y) (0 for double storage).
+template <class S>
+__host__ __device__ inline double ref_offset(const S* __restrict__ f, int nx, int y, int x) {
   if constexpr (sizeof(S) == 4) {
-    return (double)ref_plane(f, plane)[k];
+    return (double)ref_base(f)[ref_at(nx, y, x)];
   } else {
     return 0.0;
   }
@@ -172,16 +189,14 @@ template <class S>
 __host__ __device__ inline void dest_refs(const StepParams& p, const S* __restrict__ f, const uint8_t* __restrict__ mask,
                                           int x, int y, double c[9]) {
   if constexpr (sizeof(S) == 4) {
-    const size_t plane = (size_t)p.nx * p.ny;
-    const size_t self = (size_t)y * p.nx + x;
-    const double c_self = ref_offset<S>(f, plane, self);
+    const double c_self = ref_offset<S>(f, p.nx, y, x);
     c[0] = c_self;
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
       int xd, yd;
       bool inside;
       const bool sol = solid_at(p, mask, x + ex(i), y + ey(i), xd, yd, inside);
-      c[i] = sol ? c_self : ref_offset<S>(f, plane, (size_t)yd * p.nx + xd);
+      c[i] = sol ? c_self : ref_offset<S>(f, p.nx, yd, xd);
     }
   } else {
 #pragma unroll
@@ -202,30 +217,27 @@ template <class S>
 __host__ __device__ inline void pull_node(const StepParams& p, const S* __restrict__ f, const uint8_t* __restrict__ mask,
                                           const double* __restrict__ wall_u, int x, int y, double d[9], double* wall,
                                           double& c, float* cdst = nullptr, unsigned* sbits = nullptr) {
-  const size_t plane = (size_t)p.nx * p.ny;
-  const size_t self = (size_t)y * p.nx + x;
+  const int nx = p.nx;
+  const size_t plane = (size_t)nx * p.ny;  // of the wall-velocity field
   // every population gathered here was stored relative to this node's offset
-  const double c_self = ref_offset<S>(f, plane, self);
+  const double c_self = ref_offset<S>(f, nx, y, x);
   c = c_self;
   bool sol[9], ins[9];
-  size_t ks[9];
+  int xs[9], ys[9];
   sol[0] = false;
   ins[0] = true;
-  ks[0] = self;
+  xs[0] = x;
+  ys[0] = y;
 #pragma unroll
-  for (int i = 1; i < 9; ++i) {
-    int xs, ys;
-    sol[i] = solid_at(p, mask, x - ex(i), y - ey(i), xs, ys, ins[i]);
-    ks[i] = (size_t)ys * p.nx + xs;
-  }
+  for (int i = 1; i < 9; ++i) sol[i] = solid_at(p, mask, x - ex(i), y - ey(i), xs[i], ys[i], ins[i]);
   if (sbits) {
     unsigned b = 0;
 #pragma unroll
     for (int i = 1; i < 9; ++i) b |= sol[i] ? (1u << i) : 0u;
     *sbits = b;
   }
-  // offsets of the pullers: every index is in the box (solid_at wraps even
-  // across a non-periodic edge), so the loads are unconditional
+  // offsets of the pullers: every position is in the box (solid_at wraps
+  // even across a non-periodic edge), so the loads are unconditional
   double cd[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) cd[i] = 0.0;
@@ -234,19 +246,19 @@ __host__ __device__ inline void pull_node(const StepParams& p, const S* __restri
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         const int j = opp(i);
-        const double cj = ref_offset<S>(f, plane, ks[j]);
+        const double cj = ref_offset<S>(f, nx, ys[j], xs[j]);
         cd[i] = sol[j] ? c_self : cj;
         cdst[i] = (float)cd[i];
       }
     }
   }
-  d[0] = (double)f[self];
+  d[0] = (double)f[pop_at<S>(nx, y, 0, x)];
   double rho_w = 0.0;
   bool have_rho_w = false;
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
     // the pulled population, or the node's own opposite one across a wall
-    const size_t src = sol[i] ? (size_t)opp(i) * plane + self : (size_t)i * plane + ks[i];
+    const size_t src = sol[i] ? pop_at<S>(nx, y, opp(i), x) : pop_at<S>(nx, ys[i], i, xs[i]);
     double v = (double)f[src];
     if (sol[i]) {
       double mw = 0.0;
@@ -256,16 +268,18 @@ __host__ __device__ inline void pull_node(const StepParams& p, const S* __restri
           if constexpr (sizeof(S) == 4) {
             if (!cdst) {
 #pragma unroll
-              for (int q = 0; q < 9; ++q) cd[q] = sol[opp(q)] ? c_self : ref_offset<S>(f, plane, ks[opp(q)]);
+              for (int q = 0; q < 9; ++q)
+                cd[q] = sol[opp(q)] ? c_self : ref_offset<S>(f, nx, ys[opp(q)], xs[opp(q)]);
             }
           }
           double s = 0.0;
 #pragma unroll
-          for (int q = 0; q < 9; ++q) s += (double)f[(size_t)q * plane + self] + wgt(q) * cd[q];
+          for (int q = 0; q < 9; ++q) s += (double)f[pop_at<S>(nx, y, q, x)] + wgt(q) * cd[q];
           rho_w = p.rho_ref + s;
           have_rho_w = true;
         }
-        double eu = ex(i) * wall_u[ks[i]] + ey(i) * wall_u[plane + ks[i]];
+        const size_t ks = (size_t)ys[i] * nx + xs[i];
+        double eu = ex(i) * wall_u[ks] + ey(i) * wall_u[plane + ks];
         mw = 6.0 * wgt(i) * rho_w * eu;
         v += mw;
       }

@@ -143,10 +143,11 @@ class Lattice:
         self._check(L.lbm_state_bytes(C.byref(self.cfg), C.byref(sb)), None)
         self._check(L.lbm_workspace_bytes(C.byref(self.cfg), C.byref(wb)), None)
         self.dtype = torch.float64 if precision == FP64 else torch.float32
-        # 9 population planes; float storage adds the per-node reference plane
+        # rows of planes, [ny][planes][nx]: 9 populations; float storage adds a
+        # run of per-node reference offsets
         planes = sb.value // (nx * ny * (8 if precision == FP64 else 4))
-        self.f_a = torch.empty((planes, ny, nx), dtype=self.dtype, device=self.device)
-        self.f_b = torch.empty((planes, ny, nx), dtype=self.dtype, device=self.device)
+        self.f_a = torch.empty((ny, planes, nx), dtype=self.dtype, device=self.device)
+        self.f_b = torch.empty((ny, planes, nx), dtype=self.dtype, device=self.device)
         assert self.f_a.numel() * self.f_a.element_size() == sb.value
         # torch's caching allocator returns >= 512-byte aligned blocks
         self.workspace = torch.empty(wb.value, dtype=torch.uint8, device=self.device)
@@ -247,13 +248,16 @@ class Lattice:
         self._check(lib().lbm_rereference(self.h), self.h)
 
     def state(self) -> torch.Tensor:
-        """The array that holds the current state: 9 population planes (FP32_DEV: stored
-        relative to the reference densities whose offsets the tenth plane holds)."""
+        """The current state as a [planes][ny][nx] view of the array that holds it: 9
+        population planes (FP32_DEV: stored relative to the reference densities whose
+        offsets, as 16-bit floats, plane 9 holds)."""
         p = C.c_void_p(0)
         self._check(lib().lbm_state_ptr(self.h, C.byref(p)), self.h)
-        return self.f_a if p.value == self.f_a.data_ptr() else self.f_b
+        f = self.f_a if p.value == self.f_a.data_ptr() else self.f_b
+        return f.permute(1, 0, 2)
 
     def get_state(self) -> torch.Tensor:
+        """A copy of the state in the library's layout ([ny][planes][nx]), for set_state."""
         dst = torch.empty_like(self.f_a)
         self._check(lib().lbm_get_state(self.h, _ptr(dst)), self.h)
         return dst
