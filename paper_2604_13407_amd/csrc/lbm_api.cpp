@@ -123,20 +123,28 @@ bool config_ok(const lbm_config* c, std::string& why) {
 constexpr int kMinSegLen = 4;
 
 // Rows each wavefront marches: the longest of 24, 16, 12, 8, 6 rows that
-// still gives the launch enough wavefronts to fill the chip (2,048 for float
-// storage, 1,024 for double, whose rows carry twice the bytes).  A run
-// recomputes the pseudopotential of the two rows beside it, so longer runs
-// read less; but a run keeps only a few rows of loads in flight, so the chip
-// needs many runs at once.  Measured on gfx950: 2048 x 16384, float: 24 rows
-// 64.4k MLUPS, 16 rows 63.7k, 64 rows ~15% slower; 512 x 2048, float: 8 rows
-// 48.5k, 16 rows 42.2k; double: 16 rows 35.2k, 8 rows 33.4k.
+// still gives the launch enough wavefronts to fill the chip (2,560 for float
+// storage, which fits 3 per SIMD, 1,024 for double).  A run recomputes the
+// pseudopotential of the two rows beside it, so longer runs read and compute
+// less; but a run keeps only a few rows of loads in flight, so the chip needs
+// many runs at once.  Lattices whose two population arrays exceed the 256 MB
+// last-level cache stream from HBM, and there short runs are faster: the
+// waves resident at one time then read fewer, fuller DRAM rows.  Those take
+// at most 12 rows (float) or 8 (double).  Measured on gfx950 (MLUPS):
+// 2048 x 16384, float: 8 rows 63.2k, 12 64.3k, 16 63.9k, 24 61.8k, 32 62.0k;
+// double: 4 rows 34.3k, 8 35.6k, 16 34.9k, 24 34.0k.  512 x 2048 (cache
+// resident), float: 8 rows 48.5k, 16 rows 42.2k; double: 16 rows 35.2k, 8
+// rows 33.4k.
 int default_seg_len(const lbm_lattice* h) {
   const int nx = h->cfg.nx, ny = std::max(h->cfg.ny, 1);
   int n_strips, n_segs;
   const bool aligned = pplbm::aligned_strips(nx, fast_path(h) ? 1 : 0);
-  // enough wavefronts for ~2 (FP64) or ~2.5 (FP32, which fits 3) per SIMD of the 1,024
-  const long target = h->cfg.precision == LBM_FP64 ? 1024 : 2560;
+  const bool fp64 = h->cfg.precision == LBM_FP64;
+  const long target = fp64 ? 1024 : 2560;
+  const bool streams = 2.0 * (double)state_bytes_of(&h->cfg) > 256.0 * 1048576.0;
+  const int cap = streams ? (fp64 ? 8 : 12) : 24;
   for (int rows : {24, 16, 12, 8, 6}) {
+    if (rows > cap) continue;
     pplbm::fused_shape(nx, ny, rows, aligned, &n_strips, &n_segs);
     if ((long)n_strips * n_segs >= target) return std::min(rows, ny);
   }
