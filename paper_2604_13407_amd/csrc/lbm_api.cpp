@@ -48,6 +48,10 @@ bool fast_path(const lbm_lattice* h) {
   return h->cfg.kernel == LBM_KERNEL_FUSED && !h->buf.mask && !h->buf.wall_u && bytes < 4294967040.0;
 }
 
+// Whether the two population arrays exceed the 256 MB last-level cache, so
+// that every step streams them from HBM.
+bool streams_from_hbm(const lbm_config* c) { return 2.0 * (double)state_bytes_of(c) > 256.0 * 1048576.0; }
+
 bool replay_writes_traj(const lbm_lattice* h) {
   // the aligned strip kernel, with 32-bit byte offsets into the trajectory
   return fast_path(h) && pplbm::aligned_strips(h->cfg.nx, 1) &&
@@ -67,6 +71,7 @@ hipError_t step_between(lbm_lattice* h, const void* f_in, void* f_out, int reduc
   L.reduce = reduce;
   L.fast = fast_path(h) ? 1 : 0;
   L.traj = traj;
+  L.interleave = (h->cfg.precision == LBM_FP32_DEV && streams_from_hbm(&h->cfg)) ? 1 : 0;
   return (h->cfg.precision == LBM_FP64) ? pplbm::launch_step<double>(h->prm, L, h->stream)
                                         : pplbm::launch_step<float>(h->prm, L, h->stream);
 }
@@ -141,8 +146,7 @@ int default_seg_len(const lbm_lattice* h) {
   const bool aligned = pplbm::aligned_strips(nx, fast_path(h) ? 1 : 0);
   const bool fp64 = h->cfg.precision == LBM_FP64;
   const long target = fp64 ? 1024 : 2560;
-  const bool streams = 2.0 * (double)state_bytes_of(&h->cfg) > 256.0 * 1048576.0;
-  const int cap = streams ? (fp64 ? 8 : 12) : 24;
+  const int cap = streams_from_hbm(&h->cfg) ? (fp64 ? 8 : 12) : 24;
   for (int rows : {24, 16, 12, 8, 6}) {
     if (rows > cap) continue;
     pplbm::fused_shape(nx, ny, rows, aligned, &n_strips, &n_segs);

@@ -21,6 +21,8 @@ struct StepLaunch {
   int fast;           // fused: use the specialised strip kernel (no mask, no moving walls, 32-bit offsets)
   double* traj;       // adjoint replay: also write rho - rho_ref, j_x, j_y, psi per node ([4][ny][nx]);
                       // aligned strip kernel only, without reductions; NULL otherwise
+  int interleave;     // aligned strip kernel: the XCDs take successive runs of rows in turn (0: each XCD
+                      // takes one contiguous band of runs)
 };
 
 int two_pass_blocks(int nx, int ny);

@@ -1160,11 +1160,23 @@ __device__ inline ColGeo col_geo(const StepParams& p, int x, bool want) {
 template <class S, bool REDUCE, bool TRAJ>
 __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __restrict__ f, S* __restrict__ fo,
                                                       int n_strips, int seg_len, int n_segs, int groups, int per_xcd,
-                                                      double* __restrict__ partials, double* __restrict__ traj) {
+                                                      int interleave, double* __restrict__ partials,
+                                                      double* __restrict__ traj) {
+  // Blocks go to the 8 XCDs round-robin (block b to XCD b mod 8).  Either
+  // each XCD takes one contiguous band of runs, neighbouring runs sharing its
+  // L2, or (interleave) the XCDs take successive runs in turn, so that all of
+  // them stream from the same few DRAM rows at a time.
   const int b = blockIdx.x;
-  const int L = (b & 7) * per_xcd + (b >> 3);
-  const int seg = L / groups;
-  const int group = L - seg * groups;
+  int seg, group;
+  if (interleave) {
+    const int i = b >> 3, q = i / groups;
+    seg = 8 * q + (b & 7);
+    group = i - q * groups;
+  } else {
+    const int L = (b & 7) * per_xcd + (b >> 3);
+    seg = L / groups;
+    group = L - seg * groups;
+  }
   const int wv = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int strip = group * 4 + wv;
@@ -1319,17 +1331,19 @@ hipError_t launch_step(const StepParams& p, const StepLaunch& L, hipStream_t st)
     fused_shape(p.nx, p.ny, L.seg_len, true, &n_strips, &n_segs);
     int groups = (n_strips + 3) / 4;
     int total = groups * n_segs;
-    int per_xcd = (total + 7) / 8;
+    // blocks per XCD: interleaved, every strip group of ceil(n_segs / 8) runs
+    int per_xcd = L.interleave ? groups * ((n_segs + 7) / 8) : (total + 7) / 8;
+    const int il = L.interleave ? 1 : 0;
     if (L.traj && L.reduce) return hipErrorInvalidValue;
     if (L.traj)
       hipLaunchKernelGGL((aligned_kernel<S, false, true>), dim3(8 * per_xcd), dim3(256), 0, st, p, f, fo, n_strips,
-                         L.seg_len, n_segs, groups, per_xcd, L.partials, L.traj);
+                         L.seg_len, n_segs, groups, per_xcd, il, L.partials, L.traj);
     else if (L.reduce)
       hipLaunchKernelGGL((aligned_kernel<S, true, false>), dim3(8 * per_xcd), dim3(256), 0, st, p, f, fo, n_strips,
-                         L.seg_len, n_segs, groups, per_xcd, L.partials, nullptr);
+                         L.seg_len, n_segs, groups, per_xcd, il, L.partials, nullptr);
     else
       hipLaunchKernelGGL((aligned_kernel<S, false, false>), dim3(8 * per_xcd), dim3(256), 0, st, p, f, fo, n_strips,
-                         L.seg_len, n_segs, groups, per_xcd, L.partials, nullptr);
+                         L.seg_len, n_segs, groups, per_xcd, il, L.partials, nullptr);
   } else if (L.fast && launch_fast62<S>(p, L, st)) {
     // launched: the 62-column strip kernel (double storage, widths not a multiple of 64)
   } else {
