@@ -188,7 +188,8 @@ int lbm_step(lbm_lattice* h, int64_t n, int32_t reduce_every, lbm_reduction* out
  * moving walls): rows each wavefront marches through (4 <= rows <= 4096; 0
  * restores the default chosen from the lattice size and precision).  The
  * tile kernel of other lattices does not use it.
- * Results do not depend on it. */
+ * The state does not depend on it; reductions may differ in the last bits,
+ * since their partial sums are grouped by run. */
 int lbm_set_rows_per_wave(lbm_lattice* h, int32_t rows);
 
 /* Steps taken since lbm_init_equilibrium / lbm_set_state. */
