@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 2
+#define LBM_ABI_VERSION 3
 
 enum lbm_status {
   LBM_OK = 0,
@@ -221,8 +221,16 @@ int lbm_set_state(lbm_lattice* h, const void* src_dev, int64_t step);
  * sum of its post-collision populations) and re-express the stored
  * populations against it (one more rounding each); for long runs in which
  * the density moves far from where it started.  No-op for LBM_FP64.  Enqueues
- * one kernel; invalidates a recorded adjoint forward pass. */
+ * three kernels; invalidates a recorded adjoint forward pass. */
 int lbm_rereference(lbm_lattice* h);
+
+/* LBM_FP32_DEV: lbm_step re-references (as lbm_rereference, after the step,
+ * so the step's reductions are unaffected) after every step whose count is a
+ * multiple of k; k = 0 never.  Default 1000: without it the references of a
+ * moving interface go stale and the rounding of the stored deviations
+ * accumulates over long runs.  The adjoint's forward pass and replay do not
+ * re-reference.  No effect for LBM_FP64.  k < 0: LBM_ERR_INVALID_ARG. */
+int lbm_set_rereference_every(lbm_lattice* h, int64_t k);
 
 /* ---------------------------------------------------------------------------
  * Discrete adjoint (reverse-mode gradients of a loss of a run).

@@ -32,6 +32,9 @@ struct lbm_lattice {
   double rho_s;
   int cur = 0;  // 0: f_a holds the current state, 1: f_b
   int64_t steps = 0;
+  // float storage: lbm_step re-references after every step whose count is a
+  // multiple of this (0: never)
+  int64_t reref_every = 0;
   bool initialized = false;
   int seg_len = 64;
   // workspace carve-up

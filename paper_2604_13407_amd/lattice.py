@@ -37,7 +37,8 @@ EXPORTS = ("lbm_abi_version", "lbm_state_bytes", "lbm_workspace_bytes", "lbm_cre
            "lbm_set_body_force", "lbm_set_phase_densities", "lbm_set_walls", "lbm_init_equilibrium", "lbm_step",
            "lbm_set_rows_per_wave",
            "lbm_step_count", "lbm_read_fields", "lbm_reduce", "lbm_state_ptr", "lbm_get_state", "lbm_set_state",
-           "lbm_rereference", "lbm_adjoint_workspace_bytes", "lbm_adjoint_forward", "lbm_adjoint_backward")
+           "lbm_rereference", "lbm_set_rereference_every", "lbm_adjoint_workspace_bytes", "lbm_adjoint_forward",
+           "lbm_adjoint_backward")
 
 
 class LbmError(RuntimeError):
@@ -106,6 +107,7 @@ def lib():
         L.lbm_get_state.argtypes = [vp, vp]
         L.lbm_set_state.argtypes = [vp, vp, C.c_int64]
         L.lbm_rereference.argtypes = [vp]
+        L.lbm_set_rereference_every.argtypes = [vp, C.c_int64]
         L.lbm_adjoint_workspace_bytes.argtypes = [C.POINTER(Config), C.POINTER(AdjointConfig), C.POINTER(C.c_size_t)]
         L.lbm_adjoint_forward.argtypes = [vp, C.POINTER(AdjointConfig), vp, vp, C.c_size_t, dp]
         L.lbm_adjoint_backward.argtypes = [vp, vp, dp, dp]
@@ -246,6 +248,11 @@ class Lattice:
     def rereference(self):
         """Float storage: make every node's reference density its current density."""
         self._check(lib().lbm_rereference(self.h), self.h)
+
+    def set_rereference_every(self, k: int):
+        """Float storage: step() re-references after every step whose count is a multiple
+        of k (0: never; default 1000)."""
+        self._check(lib().lbm_set_rereference_every(self.h, k), self.h)
 
     def state(self) -> torch.Tensor:
         """The current state as a [planes][ny][nx] view of the array that holds it: 9

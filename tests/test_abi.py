@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(LT.EXPORTS)
-    assert L.lbm_abi_version() == 2
+    assert L.lbm_abi_version() == 3
 
 
 def cfg(**kw):
@@ -92,6 +92,8 @@ def test_setters_validate_and_state_errors_without_a_gpu():
         assert L.lbm_reduce(h, C.byref(r)) == -6
         assert L.lbm_get_state(h, C.c_void_p(0x5000)) == -6
         assert L.lbm_rereference(h) == -6
+        assert L.lbm_set_rereference_every(h, -1) == -1 and L.lbm_set_rereference_every(h, 0) == 0
+        assert L.lbm_set_rereference_every(h, 1000) == 0
         assert L.lbm_init_equilibrium(h, None, None, None) == -1
         assert "NULL" in L.lbm_last_error(h).decode()
         n = C.c_int64(-1)

@@ -312,6 +312,31 @@ def test_rows_per_wave_do_not_change_results(precision, make):
             assert a["mass"] == pytest.approx(b["mass"], rel=1e-14)
 
 
+@pytest.mark.parametrize("make", [droplet_aligned, annulus_small])
+def test_automatic_rereference_is_the_explicit_one(make):
+    """Float storage: the re-reference lbm_step makes after every k-th step is the
+    explicit one after the same steps, and leaves that step's reductions alone."""
+    w = make()
+    a = LT.Lattice.from_workload(w, precision=LT.FP32_DEV)
+    a.set_rereference_every(15)
+    ra = a.step(34, reduce_every=5)
+    b = LT.Lattice.from_workload(w, precision=LT.FP32_DEV)
+    b.set_rereference_every(0)
+    rb = b.step(15, reduce_every=5)
+    b.rereference()
+    rb += b.step(15, reduce_every=5)
+    b.rereference()
+    rb += b.step(4, reduce_every=5)
+    torch.cuda.synchronize()
+    assert torch.equal(a.state(), b.state())
+    assert ra == rb
+    c = LT.Lattice.from_workload(w, precision=LT.FP32_DEV)
+    c.set_rereference_every(0)
+    c.step(34)
+    torch.cuda.synchronize()
+    assert not torch.equal(a.state()[9], c.state()[9])  # the references moved
+
+
 @pytest.mark.parametrize("make", [droplet_small, droplet_aligned, annulus_small])
 def test_rereference_keeps_the_run(make):
     """Float storage: re-referencing every node to its current density changes the
