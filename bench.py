@@ -211,7 +211,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "storage": "f32 deviations from w_i times per-node reference densities",
+        "storage": "f32 deviations from w_i times per-node reference densities, re-referenced every 1000 steps",
         "data": "synthetic",
         "config": {"workload": "droplet channel 2048x16384, CS EOS T=0.7Tc, R=256 droplet, buoyant g=1e-7, "
                                "improved scheme eps=1.895, reductions every 100 steps",
