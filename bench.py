@@ -150,9 +150,20 @@ def cpu_baseline(w, target_s=20.0):
     o.step(n)
     dt = time.perf_counter() - t0
     nodes = w.nx * band
+    # the same band on one thread, a few steps
+    O.lib().oracle_threads(1)
+    try:
+        n1 = max(1, int(0.2 * target_s / (per_step * threads)))
+        t1 = time.perf_counter()
+        o.step(n1)
+        dt1 = time.perf_counter() - t1
+    finally:
+        O.lib().oracle_threads(threads)
     return {"value": nodes * n / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "value_1_thread": nodes * n1 / dt1 / 1e6, "nproc": os.cpu_count(),
             "sample": f"FP64 oracle, {w.nx}x{band} band of the droplet lattice (rows {y0}..{y0 + band - 1}, "
-                      f"walls in x, periodic in y), {n} steps, {dt:.1f} s, {threads} threads"}
+                      f"walls in x, periodic in y), {n} steps, {dt:.1f} s, {threads} threads; "
+                      f"{n1} steps on 1 thread, {dt1:.1f} s"}
 
 
 def copy_calibration():
