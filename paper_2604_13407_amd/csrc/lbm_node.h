@@ -139,10 +139,12 @@ __host__ __device__ constexpr int state_planes() {
   return sizeof(S) == 4 ? 10 : 9;
 }
 
-// Element index of population i of node (x, y).
+// Element index of population i of node (x, y).  Lattices have 9 nx ny <
+// 2^31 (checked at creation), so with at most 10 planes every element index
+// fits 32 bits; 32-bit products are cheaper than 64-bit ones.
 template <class S>
 __host__ __device__ inline size_t pop_at(int nx, int y, int i, int x) {
-  return ((size_t)y * state_planes<S>() + (size_t)i) * (size_t)nx + (size_t)x;
+  return (size_t)(((unsigned)y * (unsigned)state_planes<S>() + (unsigned)i) * (unsigned)nx + (unsigned)x);
 }
 
 typedef _Float16 RefT;
@@ -150,7 +152,8 @@ typedef _Float16 RefT;
 // Index, in 16-bit units of a float population array, of node (x, y)'s
 // reference offset.
 __host__ __device__ inline size_t ref_at(int nx, int y, int x) {
-  return 2 * ((size_t)y * 10 + 9) * (size_t)nx + (size_t)x;
+  // the float element index of the row's tenth run fits 32 bits; doubled, it may not
+  return 2 * (size_t)(((unsigned)y * 10u + 9u) * (unsigned)nx) + (size_t)x;
 }
 
 template <class S>
