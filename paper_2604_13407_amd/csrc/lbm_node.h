@@ -122,7 +122,7 @@ __host__ __device__ inline bool solid_at(const StepParams& p, const uint8_t* __r
   xw = x;
   yw = y;
   if (!inside) return true;
-  return mask ? (mask[(size_t)y * p.nx + x] != 0) : false;
+  return mask ? (mask[(unsigned)y * (unsigned)p.nx + (unsigned)x] != 0) : false;  // nx ny < 2^31
 }
 
 // Layout of a population array: rows of planes.  Row y holds P runs of nx
@@ -281,7 +281,7 @@ __host__ __device__ inline void pull_node(const StepParams& p, const S* __restri
           rho_w = p.rho_ref + s;
           have_rho_w = true;
         }
-        const size_t ks = (size_t)ys[i] * nx + xs[i];
+        const size_t ks = (unsigned)ys[i] * (unsigned)nx + (unsigned)xs[i];
         double eu = ex(i) * wall_u[ks] + ey(i) * wall_u[plane + ks];
         mw = 6.0 * wgt(i) * rho_w * eu;
         v += mw;
