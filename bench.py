@@ -58,6 +58,12 @@ def parse():
                     help="steps of the adjoint run (default: the workload's 20,000)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for HBM counter scaling)")
+    ap.add_argument("--accuracy-steps", type=int, default=0,
+                    help="instead of timing: run the FP32-storage and FP64 paths side by side for this many "
+                         "steps and print their max-norm differences (one JSON line per checkpoint)")
+    ap.add_argument("--accuracy-every", type=int, default=20000, help="checkpoint interval of --accuracy-steps")
+    ap.add_argument("--rereference-every", type=int, default=-1,
+                    help="FP32 storage re-reference interval for --accuracy-steps (default: the library's)")
     return ap.parse_args()
 
 
@@ -178,6 +184,34 @@ def copy_calibration():
     return {"bytes_read": 1 << 30, "bytes_written": 1 << 30, "launches": 3}
 
 
+def accuracy_run(w, total, every, reref):
+    """FP32 storage against FP64 on the GPU over a long run of the same workload:
+    max-norm relative density and velocity (of the FP64 peak) differences, the
+    droplet velocity U_c and the mass, at every checkpoint."""
+    import torch
+    from paper_2604_13407_amd import lattice as LT
+    a = LT.Lattice.from_workload(w, precision=LT.FP32_DEV)
+    if reref >= 0:
+        a.set_rereference_every(reref)
+    b = LT.Lattice.from_workload(w, precision=LT.FP64)
+    done = 0
+    while done < total:
+        n = min(every, total - done)
+        ra = a.step(n, reduce_every=w.reduce_every)
+        rb = b.step(n, reduce_every=w.reduce_every)
+        done += n
+        fa, fb = a.read_fields(), b.read_fields()
+        peak = torch.sqrt(fb["ux"] ** 2 + fb["uy"] ** 2).max().item()
+        du = torch.sqrt((fa["ux"] - fb["ux"]) ** 2 + (fa["uy"] - fb["uy"]) ** 2).max().item()
+        drho = ((fa["rho"] - fb["rho"]).abs() / fb["rho"]).max().item()
+        uca, ucb = ra[-1]["uc_num"] / ra[-1]["uc_den"], rb[-1]["uc_num"] / rb[-1]["uc_den"]
+        print(json.dumps({"steps": done, "rho_rel_max": drho, "u_max_over_peak": du / peak, "u_peak": peak,
+                          "Uc_fp32": uca, "Uc_fp64": ucb, "Uc_rel": abs(uca - ucb) / abs(ucb),
+                          "mass_rel": abs(ra[-1]["mass"] - rb[-1]["mass"]) / rb[-1]["mass"],
+                          "rereference_every": reref if reref >= 0 else "default"}), flush=True)
+        del fa, fb
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -194,6 +228,9 @@ def main():
     steps, warmup = args.steps, args.warmup
     if args.adjoint_only:
         print(json.dumps({"adjoint": adjoint_run(args.adjoint_steps)}), flush=True)
+        return
+    if args.accuracy_steps > 0:
+        accuracy_run(w, args.accuracy_steps, args.accuracy_every, args.rereference_every)
         return
     if args.fp64_only:
         r = gpu_run(w, LT.FP64, steps, warmup, reduce_every)
