@@ -272,6 +272,10 @@ def main():
                              "the timed region, on the lattice's stream); traffic = HBM bytes per launch from "
                              "rocprofv3 FETCH_SIZE/WRITE_SIZE scaled by a plain copy (profiles/)"},
     }
+    traffic = result["roofline"]["traffic"]
+    if traffic:
+        # the counted HBM bytes of one launch over the same average step time
+        result["roofline"]["traffic_GBs"] = round(traffic / (ms * 1e-3) / 1e9, 1)
     if head["faults"]:
         result["faults"] = head["faults"]
 
