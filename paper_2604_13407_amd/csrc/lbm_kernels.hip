@@ -1086,45 +1086,25 @@ __device__ inline void amarch_row(const AMarch& m, int y, const ASlot<S>& s0, co
   }
 }
 
-// The march over rows y0 .. y1-1.  Float storage keeps three row slots (row
-// y+2 in flight while row y collides), double storage four (rows y+2, y+3).
+// The march over rows y0 .. y1-1, with three row slots: row y+2 in flight
+// while row y collides.  (A fourth slot, rows y+2 and y+3 in flight, measured
+// the same or slower for both storages once runs are short.)
 template <class S, bool REDUCE, bool TRAJ, bool INTERIOR>
 __device__ inline void amarch(const StepParams& p, const AMarch& m, int y0, double* acc) {
-  if (sizeof(S) == 4) {
-    ASlot<S> sa, sb, sc;
-    ARow ta, tb, tc;
-    // row r lives in slot (r - y0 + 1) mod 3: y0-1 -> c, y0 -> a, y0+1 -> b
-    aissue_row<S, INTERIOR>(p, m, y0 - 1, true, sc, tc.g);
-    aissue_row<S, INTERIOR>(p, m, y0, true, sa, ta.g);
-    aissue_row<S, INTERIOR>(p, m, y0 + 1, true, sb, tb.g);
-    arow_state<S>(p, m, sc, tc);
-    arow_state<S>(p, m, sa, ta);
-    for (int y = y0; y < m.y1; y += 3) {
-      amarch_row<S, REDUCE, TRAJ, INTERIOR, 2>(m, y, sa, sb, sc, tc, ta, tb, tc, acc);
-      if (y + 1 >= m.y1) break;
-      amarch_row<S, REDUCE, TRAJ, INTERIOR, 2>(m, y + 1, sb, sc, sa, ta, tb, tc, ta, acc);
-      if (y + 2 >= m.y1) break;
-      amarch_row<S, REDUCE, TRAJ, INTERIOR, 2>(m, y + 2, sc, sa, sb, tb, tc, ta, tb, acc);
-    }
-  } else {
-    ASlot<S> s0, s1, s2, s3;
-    ARow t0, t1, t2, t3;
-    // row r lives in slot (r - y0 + 1) mod 4: y0-1 -> 0, y0 -> 1, y0+1 -> 2, y0+2 -> 3
-    aissue_row<S, INTERIOR>(p, m, y0 - 1, true, s0, t0.g);
-    aissue_row<S, INTERIOR>(p, m, y0, true, s1, t1.g);
-    aissue_row<S, INTERIOR>(p, m, y0 + 1, true, s2, t2.g);
-    aissue_row<S, INTERIOR>(p, m, y0 + 2, y0 + 2 <= m.y1, s3, t3.g);
-    arow_state<S>(p, m, s0, t0);
-    arow_state<S>(p, m, s1, t1);
-    for (int y = y0; y < m.y1; y += 4) {
-      amarch_row<S, REDUCE, TRAJ, INTERIOR, 3>(m, y, s1, s2, s0, t0, t1, t2, t0, acc);
-      if (y + 1 >= m.y1) break;
-      amarch_row<S, REDUCE, TRAJ, INTERIOR, 3>(m, y + 1, s2, s3, s1, t1, t2, t3, t1, acc);
-      if (y + 2 >= m.y1) break;
-      amarch_row<S, REDUCE, TRAJ, INTERIOR, 3>(m, y + 2, s3, s0, s2, t2, t3, t0, t2, acc);
-      if (y + 3 >= m.y1) break;
-      amarch_row<S, REDUCE, TRAJ, INTERIOR, 3>(m, y + 3, s0, s1, s3, t3, t0, t1, t3, acc);
-    }
+  ASlot<S> sa, sb, sc;
+  ARow ta, tb, tc;
+  // row r lives in slot (r - y0 + 1) mod 3: y0-1 -> c, y0 -> a, y0+1 -> b
+  aissue_row<S, INTERIOR>(p, m, y0 - 1, true, sc, tc.g);
+  aissue_row<S, INTERIOR>(p, m, y0, true, sa, ta.g);
+  aissue_row<S, INTERIOR>(p, m, y0 + 1, true, sb, tb.g);
+  arow_state<S>(p, m, sc, tc);
+  arow_state<S>(p, m, sa, ta);
+  for (int y = y0; y < m.y1; y += 3) {
+    amarch_row<S, REDUCE, TRAJ, INTERIOR, 2>(m, y, sa, sb, sc, tc, ta, tb, tc, acc);
+    if (y + 1 >= m.y1) break;
+    amarch_row<S, REDUCE, TRAJ, INTERIOR, 2>(m, y + 1, sb, sc, sa, ta, tb, tc, ta, acc);
+    if (y + 2 >= m.y1) break;
+    amarch_row<S, REDUCE, TRAJ, INTERIOR, 2>(m, y + 2, sc, sa, sb, tb, tc, ta, tb, acc);
   }
 }
 
