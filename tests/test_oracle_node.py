@@ -203,3 +203,38 @@ def test_improved_equals_original_at_rest_with_same_q2_policy():
     np.testing.assert_allclose(b - a, want, rtol=1e-9, atol=1e-18)
     tol = 4 * np.finfo(float).eps * r  # rounding at the scale of f
     assert abs((b - a).sum()) < tol and abs(EX @ (b - a)) < tol and abs(EY @ (b - a)) < tol
+
+
+def source_tensor(Q):
+    """The second-order source elements as the symmetric tensor that Eq. (10)
+    differentiates: [[Q1/6 + Q7/2, Q8], [Q8, Q1/6 - Q7/2]] (c = 1)."""
+    return np.array([[Q[1] / 6 + Q[7] / 2, Q[8]], [Q[8], Q[1] / 6 - Q[7] / 2]])
+
+
+@pytest.mark.parametrize("scheme", [O.SCHEME_ORIGINAL, O.SCHEME_IMPROVED])
+@pytest.mark.parametrize("k1,k2", [(None, None), (-0.07, 0.02), (0.05, -0.11)])
+def test_second_order_source_rotates_with_the_force(scheme, k1, k2):
+    # Eq. (10): Q_{m,1}, Q_{m,7}, Q_{m,8} enter the pressure tensor through one
+    # symmetric tensor built from F_int alone, so it must rotate with the force:
+    # T(R F) = R T(F) R^T for every rotation R.  Under a 45-degree turn the
+    # traceless part moves from the p_xx moment (Q_{m,7}) into the p_xy moment
+    # (Q_{m,8}), which fixes Q_{m,8} against Q_{m,7} and Q_{m,1}.
+    p = params(eps=1.895, scheme=scheme, k1=k1, k2=k2)
+    for _ in range(6):
+        F = RNG.uniform(-1e-2, 1e-2, 2)
+        psi, u, v = RNG.uniform(0.05, 1.0), RNG.uniform(-0.1, 0.1), RNG.uniform(-0.1, 0.1)
+        T0 = source_tensor(O.source(p, F[0], F[1], psi, u, v))
+        for ang in (np.pi / 4, np.pi / 6, 1.1, 2.5, -0.7):
+            R = np.array([[np.cos(ang), -np.sin(ang)], [np.sin(ang), np.cos(ang)]])
+            Fr = R @ F
+            T1 = source_tensor(O.source(p, Fr[0], Fr[1], psi, u, v))
+            np.testing.assert_allclose(T1, R @ T0 @ R.T, rtol=0, atol=1e-13 * np.abs(T0).max())
+        # the tensor is symmetric in its construction; its isotropic part carries
+        # eps = -8 (k1 + k2) (Sec. 2): trace = (k1 + 2 k2) |F|^2 / (G psi^2)
+        kk1 = -1.895 / 16 if k1 is None else k1
+        kk2 = -1.895 / 16 if k2 is None else k2
+        np.testing.assert_allclose(np.trace(T0), -(kk1 + 2 * kk2) * (F @ F) / psi ** 2, rtol=1e-13)
+        # a force along x alone leaves no p_xy source, a force along the diagonal no p_xx source
+        Qx = O.source(p, F[0], 0.0, psi, u, v)
+        Qd = O.source(p, F[0], F[0], psi, u, v)
+        assert Qx[8] == 0.0 and Qd[7] == 0.0
