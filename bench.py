@@ -49,7 +49,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and accuracy check")
+    ap.add_argument("--min-warmup-s", type=float, default=0.3,
+                    help="continue the warm-up in blocks of 50 steps until it has lasted this long")
     ap.add_argument("--no-extra", action="store_true", help="time only the FP32 headline path")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--adjoint-only", action="store_true", help="time only the adjoint (profiling)")
@@ -81,17 +83,128 @@ def time_steps(lat, steps, reduce_every):
     return e0.elapsed_time(e1), wall
 
 
-def gpu_run(w, precision, steps, warmup, reduce_every):
+def warm_up(lat, warmup, reduce_every, min_s):
+    """W untimed steps, then more in blocks of 50 until the warm-up has lasted
+    min_s seconds.  After an idle spell the GPU's power management lowers the
+    shader clock a few steps into a heavy load (2.44 -> ~1.85 GHz, measured)
+    and takes ~20 steps of this workload to restore it; the float-storage step
+    kernel slows with the clock (0.70 against 0.515 ms), so K steps timed inside
+    that transient do not measure the kernel.  Returns the steps run."""
+    import torch
+    done = 0
+    t0 = time.perf_counter()
+    if warmup:
+        lat.step(warmup, reduce_every=reduce_every)
+        done += warmup
+    torch.cuda.synchronize()
+    while time.perf_counter() - t0 < min_s:
+        lat.step(50, reduce_every=reduce_every)
+        done += 50
+        torch.cuda.synchronize()
+    return done
+
+
+def gpu_run(w, precision, steps, warmup, reduce_every, min_warmup_s=0.0, keep=False):
     import torch
     from paper_2604_13407_amd import lattice as LT
     lat = LT.Lattice.from_workload(w, precision=precision, kernel=LT.KERNEL_FUSED)
-    if warmup:
-        lat.step(warmup, reduce_every=reduce_every)
+    warm = warm_up(lat, warmup, reduce_every, min_warmup_s)
     ms, wall = time_steps(lat, steps, reduce_every)
     rec = lat.reduce()
-    out = {"ms_per_step": ms / steps, "wall_s": wall, "mass": rec["mass"], "faults": rec["faults"]}
+    out = {"ms_per_step": ms / steps, "wall_s": wall, "mass": rec["mass"], "faults": rec["faults"],
+           "warmup_steps": warm, "steps_done": warm + steps}
+    if keep:
+        out["lattice"] = lat
+    else:
+        del lat
+        torch.cuda.empty_cache()
+    return out
+
+
+def cold_start(w, precision, n=40):
+    """Per-step kernel times of the first n steps of a fresh lattice after a
+    0.5 s idle spell (HIP events around each step on the lattice's stream)."""
+    import torch
+    from paper_2604_13407_amd import lattice as LT
+    lat = LT.Lattice.from_workload(w, precision=precision, kernel=LT.KERNEL_FUSED)
+    torch.cuda.synchronize()
+    time.sleep(0.5)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+    ev[0].record(lat.stream)
+    for i in range(n):
+        lat.step(1)
+        ev[i + 1].record(lat.stream)
+    torch.cuda.synchronize()
+    ts = [ev[i].elapsed_time(ev[i + 1]) for i in range(n)]
     del lat
     torch.cuda.empty_cache()
+    return ts
+
+
+def amortised_costs(w, precision, n=1000):
+    """Per-step time of n steps with the workload's reductions (every 100 steps)
+    and the library's default re-reference of float storage (every 1,000 steps),
+    against n steps with neither, on one warm lattice."""
+    import torch
+    from paper_2604_13407_amd import lattice as LT
+    lat = LT.Lattice.from_workload(w, precision=precision, kernel=LT.KERNEL_FUSED)
+    warm_up(lat, 0, 0, 0.3)
+    lat.set_rereference_every(0)
+    base, _ = time_steps(lat, n, 0)
+    lat.set_rereference_every(1000)
+    # the step count is a multiple of 50 here; align the run so that it ends
+    # with a re-reference (after step 1000k) and holds n / 100 reductions
+    pre = (-lat.step_count) % 1000
+    if pre:
+        lat.step(pre)
+    full, _ = time_steps(lat, n, w.reduce_every)
+    del lat
+    torch.cuda.empty_cache()
+    return {"steps": n, "ms_per_step_plain": round(base / n, 5),
+            "ms_per_step_with_reductions_and_rereference": round(full / n, 5),
+            "overhead": round(full / base - 1.0, 4),
+            "note": f"{n // w.reduce_every} reductions and {n // 1000} re-reference in {n} steps"}
+
+
+def accuracy_vs_oracle(w, precisions, steps, rows=64):
+    """Max-norm errors of the GPU paths against the FP64 oracle after `steps`
+    steps of the workload from its initial state: the oracle runs a band of
+    full-width rows around the droplet's upper interface grown by the light
+    cone (after k steps a node depends only on nodes within 2k of it), so the
+    band's middle `rows` rows are exact.  Density relative, velocity over the
+    oracle's peak speed in the window."""
+    import numpy as np
+    import torch
+    from oracle import oracle as O
+    from paper_2604_13407_amd import lattice as LT
+    yc = int(w.init_args["centre"][1] + w.init_args["radius"]) - rows // 2
+    m = 2 * steps + 2
+    ys = np.arange(yc - m, yc + rows + m) % w.ny
+    gpu = {}
+    for prec in precisions:
+        lat = LT.Lattice.from_workload(w, precision=prec, kernel=LT.KERNEL_FUSED)
+        lat.step(steps, reduce_every=w.reduce_every)
+        gpu[prec] = {k: v[yc:yc + rows].cpu().numpy() for k, v in lat.read_fields().items()
+                     if k in ("rho", "ux", "uy")}
+        del lat
+        torch.cuda.empty_cache()
+    p = O.Params(nx=w.nx, ny=len(ys), periodic_x=w.periodic_x, periodic_y=True, eos_kind=w.eos_kind, a=w.a,
+                 b=w.b, R=w.R, T=w.T, k_eos=w.k_eos, G=w.G, s=tuple(w.s), scheme=w.scheme, eps=w.eps, k1=w.k1,
+                 k2=w.k2, force_mode=w.force_mode, fx=w.fx, fy=w.fy, rho_g=w.rho_g, rho_l=w.rho_l, rho_s=w.rho_s)
+    o = O.Oracle(p).init(np.ascontiguousarray(w.rho0()[ys]))
+    t0 = time.perf_counter()
+    o.step(steps)
+    om = o.macros()
+    dt = time.perf_counter() - t0
+    r = {k: om[k][m:m + rows] for k in ("rho", "ux", "uy")}
+    peak = float(np.sqrt(r["ux"] ** 2 + r["uy"] ** 2).max())
+    out = {"steps": steps, "window": f"rows {yc}..{yc + rows - 1} (the droplet's upper interface), all "
+                                     f"{w.nx} columns; oracle band of {len(ys)} rows, {dt:.1f} s",
+           "u_peak": peak}
+    for prec, g in gpu.items():
+        du = float(np.sqrt((g["ux"] - r["ux"]) ** 2 + (g["uy"] - r["uy"]) ** 2).max())
+        out["fp64" if prec == LT.FP64 else "fp32"] = {
+            "rho_rel_max": float(np.max(np.abs(g["rho"] - r["rho"]) / r["rho"])), "u_max_over_peak": du / peak}
     return out
 
 
@@ -241,7 +354,7 @@ def main():
         print(json.dumps(out), flush=True)
         return
 
-    head = gpu_run(w, LT.FP32_DEV, steps, warmup, reduce_every)
+    head = gpu_run(w, LT.FP32_DEV, steps, warmup, reduce_every, args.min_warmup_s)
     ms = head["ms_per_step"]
     mlups = w.nodes / (ms * 1e-3) / 1e6
     bytes_per_node = 9 * 4 * 2  # 9 loads + 9 stores of float per node update
@@ -255,6 +368,7 @@ def main():
         "steps": steps,
         "warmup": warmup,
         "ms_per_step": round(ms, 5),
+        "warmup_steps_run": head["warmup_steps"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -280,13 +394,14 @@ def main():
         result["faults"] = head["faults"]
 
     if not args.no_extra:
-        fp64 = gpu_run(w, LT.FP64, steps, warmup, reduce_every)
+        fp64 = gpu_run(w, LT.FP64, steps, warmup, reduce_every, args.min_warmup_s)
         m64 = w.nodes / (fp64["ms_per_step"] * 1e-3) / 1e6
         a64 = w.nodes * 144 / (fp64["ms_per_step"] * 1e-3) / 1e9
         result["fp64"] = {"value": round(m64, 1), "unit": "MLUPS", "ms_per_step": round(fp64["ms_per_step"], 5),
                           "achieved_GBs": round(a64, 1), "frac": round(a64 / HBM_PEAK_GBS, 4),
                           "bytes_per_node": 144}
-        orig = gpu_run(WL.droplet(scheme=WL.SCHEME_ORIGINAL), LT.FP32_DEV, steps, warmup, reduce_every)
+        orig = gpu_run(WL.droplet(scheme=WL.SCHEME_ORIGINAL), LT.FP32_DEV, steps, warmup, reduce_every,
+                       args.min_warmup_s)
         result["original_scheme"] = {"value": round(w.nodes / (orig["ms_per_step"] * 1e-3) / 1e6, 1),
                                      "unit": "MLUPS", "ms_per_step": round(orig["ms_per_step"], 5)}
         # the other workloads (general fused kernel: solid masks, moving walls); these
@@ -296,9 +411,18 @@ def main():
                            ("annular_shear_1024x1024", WL.annular_shear)):
             wo = make()
             for prec, tag in ((LT.FP32_DEV, "fp32"), (LT.FP64, "fp64")):
-                r = gpu_run(wo, prec, steps, warmup, 0)
+                r = gpu_run(wo, prec, steps, warmup, 0, args.min_warmup_s)
                 others[f"{name}_{tag}"] = round(wo.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1)
         result["other_workloads_MLUPS"] = others
+        # the reductions and re-references a 200,000-step run of the workload makes, amortised
+        result["amortised_costs_fp32"] = amortised_costs(w, LT.FP32_DEV)
+        # the first steps after an idle spell (the power-management transient the warm-up skips)
+        cold = {}
+        for prec, tag in ((LT.FP32_DEV, "fp32"), (LT.FP64, "fp64")):
+            ts = cold_start(w, prec)
+            cold[tag] = {"ms_first_10": round(sum(ts[:10]) / 10, 4), "ms_steps_31_40": round(sum(ts[30:40]) / 10, 4),
+                         "ms_max": round(max(ts), 4)}
+        result["cold_start"] = cold
 
     if not args.no_adjoint:
         result["adjoint"] = adjoint_run(args.adjoint_steps)
@@ -307,6 +431,9 @@ def main():
         result["copy_calibration"] = copy_calibration()
 
     if not args.no_cpu:
+        # max-norm errors of both GPU paths against the oracle (after the timing)
+        acc_steps = min(head["steps_done"], 200)
+        result["accuracy_vs_oracle"] = accuracy_vs_oracle(w, (LT.FP32_DEV, LT.FP64), acc_steps)
         result["cpu_baseline"] = cpu_baseline(w)
         result["gpu_over_cpu"] = round(mlups / result["cpu_baseline"]["value"], 1)
 
