@@ -32,10 +32,13 @@ def fluid(w):
 
 
 # Scales of the FP64 comparison.  Velocity: max(|u|, U_FLOOR) with U_FLOOR a
-# typical lattice velocity (Mach ~ 0.02); j = sum e_i f_i is a difference of
-# populations of size ~rho/9, so its rounding scales with rho c, not with u.
-# Interaction force: max(|F|, 1e-3 max(psi)^2); a field that is exactly zero in
-# one ordering of the stencil sum is a few ulp of psi^2 in another.
+# typical lattice velocity (Mach ~ 0.02), i.e. the bar is 1e-12 of the peak
+# speed or 1e-14 absolute, whichever is larger: j = sum e_i f_i is a
+# difference of populations of size ~rho/9, so its rounding (and that of u)
+# scales with rho c, not with u.  The error relative to the actual peak is
+# printed.  Interaction force: max(|F|, 1e-3 max(psi)^2); a field that is
+# exactly zero in one ordering of the stencil sum is a few ulp of psi^2 in
+# another.
 U_FLOOR = 1e-2
 
 
@@ -55,6 +58,10 @@ def compare_fp64(w, g, o, tol=1e-12, fields=FIELDS):
         ref = o[k][fl]
         scale = field_scale(k, ref, psi_max)
         err = np.max(np.abs(g[k][fl] - ref)) / scale
+        if k in ("ux", "uy"):
+            peak = max(np.max(np.abs(o["ux"][fl])), np.max(np.abs(o["uy"][fl])))
+            print(f"[parity] {w.name} {k}: {np.max(np.abs(g[k][fl] - ref)):.2e} absolute, "
+                  f"{np.max(np.abs(g[k][fl] - ref)) / max(peak, 1e-300):.2e} of the peak speed {peak:.2e}", flush=True)
         assert err <= tol, (w.name, k, err)
 
 
