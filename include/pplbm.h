@@ -131,6 +131,24 @@ int lbm_workspace_bytes(const lbm_config* cfg, size_t* bytes);
  * rho_s = rho_g = 0, rho_l = 1.  Enqueues nothing.  *out is NULL on error. */
 int lbm_create(const lbm_config* cfg, const lbm_buffers* buf, void* hip_stream, lbm_lattice** out);
 
+/* Bytes of the library-owned workspace of lbm_create_static handles (32 MiB). */
+#define LBM_STATIC_WORKSPACE_BYTES ((size_t)32 << 20)
+
+/* lbm_create for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same handle, but its workspace is a library-owned static device array of
+ * LBM_STATIC_WORKSPACE_BYTES on the current device instead of a caller
+ * buffer.  buf->workspace must be NULL; the caller still owns f_a, f_b, mask,
+ * wall_u and every output.  Configurations whose lbm_workspace_bytes exceeds
+ * LBM_STATIC_WORKSPACE_BYTES (about 4 million nodes) are rejected with
+ * LBM_ERR_INVALID_ARG.  Allocates nothing: the array exists on every device
+ * the library runs on until the process ends; its address is resolved the
+ * first time this is called on a device.  Every handle made this way on one
+ * device shares that array, and a call leaves its contents for the next: calls
+ * on such handles that overlap in time (other host threads, other streams)
+ * race.  Results are those of lbm_create's handle. */
+int lbm_create_static(const lbm_config* cfg, const lbm_buffers* buf, void* hip_stream, lbm_lattice** out);
+
 /* Releases the handle (not the caller's buffers).  NULL is accepted. */
 int lbm_destroy(lbm_lattice* h);
 

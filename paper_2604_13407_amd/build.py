@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = [os.path.join(CSRC, n) for n in ("lbm_kernels.hip", "lbm_adjoint.hip", "lbm_api.cpp", "lbm_adjoint_api.cpp")]
+SOURCES = [os.path.join(CSRC, n) for n in ("lbm_kernels.hip", "lbm_adjoint.hip", "lbm_static.hip", "lbm_api.cpp",
+                                            "lbm_adjoint_api.cpp")]
 HEADERS = [os.path.join(CSRC, n) for n in ("lbm_params.h", "lbm_node.h", "lbm_internal.h", "lbm_handle.h",
                                            "lbm_adjoint_node.h", "lbm_adjoint_internal.h")] + [
     os.path.join(ROOT, "include", "pplbm.h")]

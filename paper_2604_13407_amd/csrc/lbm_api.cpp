@@ -274,6 +274,39 @@ int lbm_workspace_bytes(const lbm_config* cfg, size_t* bytes) {
   return LBM_OK;
 }
 
+int lbm_create_static(const lbm_config* cfg, const lbm_buffers* buf, void* hip_stream, lbm_lattice** out) {
+  g_create_error.clear();
+  if (!out) {
+    g_create_error = "out is NULL";
+    return LBM_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  std::string why;
+  if (!config_ok(cfg, why)) {
+    g_create_error = why;
+    return LBM_ERR_INVALID_ARG;
+  }
+  if (!buf || buf->workspace) {
+    g_create_error = "buf must be non-NULL with workspace NULL (the library's static workspace is used)";
+    return LBM_ERR_INVALID_ARG;
+  }
+  const size_t need = layout_for(cfg).total;
+  if (need > pplbm::kStaticWorkspaceBytes) {
+    g_create_error = "the lattice needs a " + std::to_string(need) + "-byte workspace; the static workspace holds " +
+                     std::to_string(pplbm::kStaticWorkspaceBytes) + " bytes (use lbm_create with a caller buffer)";
+    return LBM_ERR_INVALID_ARG;
+  }
+  void* ws = nullptr;
+  hipError_t e = pplbm::static_workspace(&ws);
+  if (e != hipSuccess) {
+    g_create_error = std::string("static workspace: ") + hipGetErrorString(e);
+    return LBM_ERR_HIP;
+  }
+  lbm_buffers b = *buf;
+  b.workspace = ws;
+  return lbm_create(cfg, &b, hip_stream, out);
+}
+
 int lbm_create(const lbm_config* cfg, const lbm_buffers* buf, void* hip_stream, lbm_lattice** out) {
   g_create_error.clear();
   if (!out) {

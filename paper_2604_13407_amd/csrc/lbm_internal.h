@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/pplbm.h"
 #include "lbm_params.h"
 
 namespace pplbm {
@@ -48,5 +49,10 @@ hipError_t launch_fields(const StepParams& p, const void* f, const uint8_t* mask
 // density (both population arrays hold the current state).
 hipError_t launch_reref(const StepParams& p, void* fa, void* fb, const uint8_t* mask, hipStream_t s);
 hipError_t launch_finalize(const double* partials, int n_parts, double* out, hipStream_t s);
+
+// Size of the library-owned workspace of lbm_create_static handles, and its
+// address on the current device (resolved once per device).
+constexpr size_t kStaticWorkspaceBytes = LBM_STATIC_WORKSPACE_BYTES;
+hipError_t static_workspace(void** ptr);
 
 }  // namespace pplbm

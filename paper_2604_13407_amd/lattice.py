@@ -38,7 +38,7 @@ EXPORTS = ("lbm_abi_version", "lbm_state_bytes", "lbm_workspace_bytes", "lbm_cre
            "lbm_set_rows_per_wave",
            "lbm_step_count", "lbm_read_fields", "lbm_reduce", "lbm_state_ptr", "lbm_get_state", "lbm_set_state",
            "lbm_rereference", "lbm_set_rereference_every", "lbm_adjoint_workspace_bytes", "lbm_adjoint_forward",
-           "lbm_adjoint_backward")
+           "lbm_adjoint_backward", "lbm_create_static")
 
 
 class LbmError(RuntimeError):
@@ -87,6 +87,7 @@ def lib():
         L.lbm_state_bytes.argtypes = [C.POINTER(Config), C.POINTER(C.c_size_t)]
         L.lbm_workspace_bytes.argtypes = [C.POINTER(Config), C.POINTER(C.c_size_t)]
         L.lbm_create.argtypes = [C.POINTER(Config), C.POINTER(Buffers), vp, C.POINTER(vp)]
+        L.lbm_create_static.argtypes = [C.POINTER(Config), C.POINTER(Buffers), vp, C.POINTER(vp)]
         L.lbm_destroy.argtypes = [vp]
         L.lbm_last_error.argtypes = [vp]
         L.lbm_last_error.restype = C.c_char_p
@@ -132,7 +133,10 @@ class Lattice:
 
     def __init__(self, nx: int, ny: int, periodic_x: bool = True, periodic_y: bool = True,
                  precision: int = FP64, kernel: int = KERNEL_FUSED, rho_ref: float = 0.0, mask=None, wall_u=None,
-                 device: str = "cuda:0", log_capacity: int = 4096, stream: Optional[torch.cuda.Stream] = None):
+                 device: str = "cuda:0", log_capacity: int = 4096, stream: Optional[torch.cuda.Stream] = None,
+                 static_workspace: bool = False):
+        """static_workspace: the handle uses the library's static device workspace
+        (lbm_create_static) instead of a workspace tensor allocated here."""
         if not torch.cuda.is_available():
             raise RuntimeError("liblbm needs a GPU: torch.cuda.is_available() is False")
         self.device = torch.device(device)
@@ -152,7 +156,7 @@ class Lattice:
         self.f_b = torch.empty((ny, planes, nx), dtype=self.dtype, device=self.device)
         assert self.f_a.numel() * self.f_a.element_size() == sb.value
         # torch's caching allocator returns >= 512-byte aligned blocks
-        self.workspace = torch.empty(wb.value, dtype=torch.uint8, device=self.device)
+        self.workspace = None if static_workspace else torch.empty(wb.value, dtype=torch.uint8, device=self.device)
         self.mask = _dev(mask, self.device, torch.uint8)
         self.wall_u = _dev(wall_u, self.device, torch.float64)
         if self.mask is not None:
@@ -160,12 +164,14 @@ class Lattice:
         if self.wall_u is not None:
             assert tuple(self.wall_u.shape) == (2, ny, nx)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.buf = Buffers(self.f_a.data_ptr(), self.f_b.data_ptr(), self.workspace.data_ptr(),
+        self.buf = Buffers(self.f_a.data_ptr(), self.f_b.data_ptr(),
+                           None if self.workspace is None else self.workspace.data_ptr(),
                            None if self.mask is None else self.mask.data_ptr(),
                            None if self.wall_u is None else self.wall_u.data_ptr())
         h = C.c_void_p(0)
         with torch.cuda.device(self.device):
-            rc = L.lbm_create(C.byref(self.cfg), C.byref(self.buf), C.c_void_p(self.stream.cuda_stream), C.byref(h))
+            create = L.lbm_create_static if static_workspace else L.lbm_create
+            rc = create(C.byref(self.cfg), C.byref(self.buf), C.c_void_p(self.stream.cuda_stream), C.byref(h))
         if rc != LBM_OK:
             raise LbmError(rc, L.lbm_last_error(None).decode())
         self.h = h

@@ -168,3 +168,19 @@ def test_adjoint_argument_and_state_errors_without_a_gpu():
                                      C.byref(out)) == -5
     finally:
         L.lbm_destroy(h)
+
+
+def test_static_workspace_rejects_lattices_beyond_its_size():
+    # lbm_create_static checks the workspace size on the host, before any device call
+    L = LT.lib()
+    big = LT.Config(2048, 2048, 1, 1, LT.FP64, LT.KERNEL_FUSED, 0.0, 16, 0)
+    buf = LT.Buffers(None, None, None, None, None)
+    h = C.c_void_p(0)
+    rc = L.lbm_create_static(C.byref(big), C.byref(buf), None, C.byref(h))
+    assert rc == -1 and not h.value
+    msg = L.lbm_last_error(None).decode()
+    assert "static workspace holds" in msg, msg
+    # a caller workspace is refused: the static variant owns it
+    small = LT.Config(64, 64, 1, 1, LT.FP64, LT.KERNEL_FUSED, 0.0, 16, 0)
+    buf2 = LT.Buffers(None, None, 256, None, None)
+    assert L.lbm_create_static(C.byref(small), C.byref(buf2), None, C.byref(h)) == -1
