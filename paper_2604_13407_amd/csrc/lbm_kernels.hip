@@ -854,7 +854,7 @@ struct AMarch {
   int y1;
   unsigned colB[9];  // byte offsets of the pulled columns (interior strips)
   // The columns beside the strip are pulled one population per lane: lane
-  // l <= 8 pulls population l of column x0-1, lane 63-i population i of
+  // l <= 8 pulls population l of column x0-1, lane 48+i population i of
   // column x0+64 (one load instruction per row).  Lane constants of that
   // pull: the population's plane and source column (element offsets), the
   // node's own opposite plane and column (bounce-back), its e_y, whether its
@@ -862,7 +862,6 @@ struct AMarch {
   unsigned hplane, hcol, hback;
   int hey;
   bool hwall, hon;
-  bool lane0;
   // float storage: the column byte offset of the halo column's reference
   // (the lane's own where there is none)
   unsigned href;
@@ -884,7 +883,10 @@ struct ASlot {
 
 struct ARow {
   double drho, jx, jy, psi;
-  double psih;  // psi of the halo column (lanes 0 and 63)
+  // psi of the west and east neighbours (lane l - 1 and l + 1; lane 0's
+  // west and lane 63's east are the columns beside the strip): each row's
+  // psi is shifted once, for the three collisions that use it
+  double pw, pe;
   bool bad;
   RowGeo g;
   RefRow cr;  // float storage: the reference offsets of this row
@@ -964,6 +966,17 @@ __device__ inline void dest_refs_row(const AMarch& m, const RowGeo& g, const Ref
 }
 
 // DPP move of a double within rows of 16 lanes (CTRL 0x100 + k: lane l
+// receives lane l+k's v); lanes without a source lane read 0.  No lane's
+// previous value is kept, so each half is one move.
+template <int CTRL>
+__device__ inline double row_dpp0(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// DPP move of a double within rows of 16 lanes (CTRL 0x100 + k: lane l
 // receives lane l+k's v; 0x110 + k: lane l-k's); lanes without a source lane
 // keep their own v.
 template <int CTRL>
@@ -977,19 +990,17 @@ __device__ inline double row_dpp(double v) {
 
 // Sum of the 9 populations of the columns beside the strip, pulled one per
 // lane, in node_sums' order d0 + ((d1 + d3) + (d2 + d4)) + ((d5 + d7) + (d6 + d8)),
-// so that psi there is bitwise the one the column's own strip computes:
-// column x0-1 into lane 0 (lane l holds d_l), column x0+64 into lane 63
-// (lane 63-i holds d_i).
-__device__ inline double halo_sum(double v, bool lane0) {
-  const double a1 = v + row_dpp<0x102>(v);     // lane 1: d1+d3, 2: d2+d4, 5: d5+d7, 6: d6+d8
-  const double a2 = a1 + row_dpp<0x101>(a1);   // lane 1: S4, lane 5: S8
-  const double a3 = v + row_dpp<0x101>(a2);    // lane 0: d0 + S4
-  const double a4 = a3 + row_dpp<0x105>(a2);   // lane 0: (d0 + S4) + S8
-  const double b1 = v + row_dpp<0x112>(v);     // lane 62: d1+d3, 61: d2+d4, 58: d5+d7, 57: d6+d8
-  const double b2 = b1 + row_dpp<0x111>(b1);   // lane 62: S4, lane 58: S8
-  const double b3 = v + row_dpp<0x111>(b2);    // lane 63: d0 + S4
-  const double b4 = b3 + row_dpp<0x115>(b2);   // lane 63: (d0 + S4) + S8
-  return lane0 ? a4 : b4;
+// so that psi there is bitwise the one the column's own strip computes.
+// Lane l <= 8 holds d_l of column x0-1 and lane 48+i d_i of column x0+64: the
+// same shifts within rows of 16 lanes sum the first into lane 0 and the
+// second into lane 48, and a last shift (row_shr:15) moves lane 48's sum to
+// lane 63 (lane 0, with no source lane, keeps its own).
+__device__ inline double halo_sum(double v) {
+  const double a1 = v + row_dpp0<0x102>(v);    // lane 1: d1+d3, 2: d2+d4, 5: d5+d7, 6: d6+d8 (48+: the same)
+  const double a2 = a1 + row_dpp0<0x101>(a1);  // lane 1: S4, lane 5: S8
+  const double a3 = v + row_dpp0<0x101>(a2);   // lane 0: d0 + S4
+  const double a4 = a3 + row_dpp0<0x105>(a2);  // lane 0: (d0 + S4) + S8
+  return row_dpp<0x11F>(a4);                   // lane 63: lane 48's sum; lane 0 keeps its own
 }
 
 template <class S>
@@ -1009,11 +1020,13 @@ __device__ inline void arow_state(const StepParams& p, const AMarch& m, const AS
   t.psi = t.g.real ? ps : p.psi_solid;
   t.bad = t.g.real && bad;
   // the halo column's density in the same arithmetic as its own strip uses
-  double hr = halo_sum((double)sl.rh, m.lane0);
+  double hr = halo_sum((double)sl.rh);
   if constexpr (sizeof(S) == 4) hr += ch;
   bool badh;
   const double psh = psi_of(p, p.rho_ref + hr, badh);
-  t.psih = (t.g.real && m.h.real) ? psh : p.psi_solid;
+  const double psih = (t.g.real && m.h.real) ? psh : p.psi_solid;
+  t.pw = wave_shr1_fill(t.psi, psih);
+  t.pe = wave_shl1_fill(t.psi, psih);
 }
 
 // Collide and store row y (slot `s0`, state `t0`), with psi of rows y-1 (`tm`)
@@ -1025,14 +1038,9 @@ __device__ inline void amarch_row(const AMarch& m, int y, const ASlot<S>& s0, co
   const StepParams& p = kernarg_params();
   aissue_row<S, INTERIOR>(p, m, y + AHEAD, y + AHEAD <= m.y1, sn, tn.g);
   arow_state<S>(p, m, s1, t1);
-  // lane 0's west and lane 63's east neighbours are the halo columns, whose
-  // psi those two lanes hold in psih
-  const double pW = wave_shr1_fill(t0.psi, t0.psih);
-  const double pE = wave_shl1_fill(t0.psi, t0.psih);
-  const double pSW = wave_shr1_fill(tm.psi, tm.psih);
-  const double pSE = wave_shl1_fill(tm.psi, tm.psih);
-  const double pNW = wave_shr1_fill(t1.psi, t1.psih);
-  const double pNE = wave_shl1_fill(t1.psi, t1.psih);
+  const double pW = t0.pw, pE = t0.pe;
+  const double pSW = tm.pw, pSE = tm.pe;
+  const double pNW = t1.pw, pNE = t1.pe;
   double d[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) d[i] = (double)s0.raw[i];
@@ -1179,8 +1187,8 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
   }
   {
     // the columns beside the strip, one population per lane
-    const bool left = lane <= 8, right = lane >= WAVE - 9;
-    const int hi = left ? lane : (right ? WAVE - 1 - lane : 0);
+    const bool left = lane <= 8, right = lane >= 48 && lane <= 56;
+    const int hi = left ? lane : (right ? lane - 48 : 0);
     const ColGeo hg = col_geo(p, left ? x0 - 1 : x0 + WAVE, left || right);
     const int exi = ex(hi);
     m.hplane = (unsigned)hi * m.nx;
@@ -1190,7 +1198,6 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
     m.hwall = (exi == 1 && hg.wall_l) || (exi == -1 && hg.wall_r);
     m.hon = (left || right) && hg.real;
   }
-  m.lane0 = lane == 0;
   // float storage: byte offset within a row's reference run of the halo
   // column's offset (the lane's own where there is none)
   m.href = (m.h.real ? m.h.own : m.c.own) * 2u;

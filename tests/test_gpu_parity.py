@@ -344,31 +344,42 @@ def test_automatic_rereference_is_the_explicit_one(make):
     assert not torch.equal(a.state()[9], c.state()[9])  # the references moved
 
 
-def test_default_rereference_keeps_a_long_run_within_the_velocity_bar():
-    """Float storage over a long run with a moving interface (the 512 x 2048 droplet
-    at g = 1e-6 falls ~200 nodes in 40,000 steps): with the default re-reference
-    every 1,000 steps the velocity stays within 1e-4 of the peak of the FP64 run;
-    without it, it does not (the references of the moving interface go stale)."""
-    w = WL.droplet_adjoint(g=1e-6)
-    steps = 40000
+def long_run_errors(w, steps, rereference=True):
+    """FP32 storage against the FP64 path after `steps` steps: (max |du| over the
+    FP64 peak speed, max relative density difference)."""
     b = LT.Lattice.from_workload(w, precision=LT.FP64)
     b.step(steps)
     fb = b.read_fields()
+    a = LT.Lattice.from_workload(w, precision=LT.FP32_DEV)
+    if not rereference:
+        a.set_rereference_every(0)
+    a.step(steps)
+    fa = a.read_fields()
     peak = torch.sqrt(fb["ux"] ** 2 + fb["uy"] ** 2).max().item()
-    err = {}
-    for k in (1000, 0):
-        a = LT.Lattice.from_workload(w, precision=LT.FP32_DEV)
-        if k == 0:
-            a.set_rereference_every(0)
-        a.step(steps)
-        fa = a.read_fields()
-        du = torch.sqrt((fa["ux"] - fb["ux"]) ** 2 + (fa["uy"] - fb["uy"]) ** 2).max().item()
-        drho = ((fa["rho"] - fb["rho"]).abs() / fb["rho"]).max().item()
-        err[k] = (du / peak, drho)
-        print(f"[long run] rereference every {k}: du/peak={du / peak:.3e} rho_rel={drho:.3e}", flush=True)
-    assert err[1000][0] <= 1e-4
-    assert err[1000][1] <= 1e-4
-    assert err[0][0] > 1e-4
+    du = torch.sqrt((fa["ux"] - fb["ux"]) ** 2 + (fa["uy"] - fb["uy"]) ** 2).max().item()
+    drho = ((fa["rho"] - fb["rho"]).abs() / fb["rho"]).max().item()
+    print(f"[long run] {w.nx}x{w.ny} g={-w.fy:g} {steps} steps rereference={rereference}: "
+          f"du/peak={du / peak:.3e} rho_rel={drho:.3e}", flush=True)
+    return du / peak, drho
+
+
+def test_default_rereference_keeps_long_runs_within_the_bars():
+    """Float storage over long runs with a moving interface (the 512 x 2048
+    falling droplet).  At the benchmark's gravity, 1e-7, 40,000 steps hold both
+    bars with the default re-reference every 1,000 steps (measured: density
+    5.2e-6 relative, velocity 1.5e-5 of the peak).  At g = 1e-6 the droplet falls
+    ~200 nodes in 40,000 steps: the velocity stays within 1e-4 of the peak with
+    the default re-reference (4.1e-5) and not without it (1.7e-4, the references
+    of the moving interface go stale), while the pointwise density difference,
+    which at a moving interface measures how far the two interfaces drifted apart
+    (1e-5 of rho there is ~1e-5 nodes), passes 1e-5 at ~20,000 steps and stays
+    below 1e-4 (7.0e-5)."""
+    du, drho = long_run_errors(WL.droplet_adjoint(g=1e-7), 40000)
+    assert du <= 1e-4 and drho <= 1e-5
+    du, drho = long_run_errors(WL.droplet_adjoint(g=1e-6), 40000)
+    assert du <= 1e-4 and drho <= 1e-4
+    du0, _ = long_run_errors(WL.droplet_adjoint(g=1e-6), 40000, rereference=False)
+    assert du0 > 1e-4
 
 
 @pytest.mark.parametrize("make", [droplet_small, droplet_aligned, annulus_small])
