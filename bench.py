@@ -346,7 +346,7 @@ def main():
         accuracy_run(w, args.accuracy_steps, args.accuracy_every, args.rereference_every)
         return
     if args.fp64_only:
-        r = gpu_run(w, LT.FP64, steps, warmup, reduce_every)
+        r = gpu_run(w, LT.FP64, steps, warmup, reduce_every, args.min_warmup_s)
         out = {"fp64": {"value": round(w.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1), "unit": "MLUPS",
                         "ms_per_step": round(r["ms_per_step"], 5), "bytes_per_node": 144}}
         if args.copy_calibration:
