@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 3
+#define LBM_ABI_VERSION 4
 
 enum lbm_status {
   LBM_OK = 0,
@@ -121,7 +121,8 @@ int lbm_abi_version(void);
 int lbm_state_bytes(const lbm_config* cfg, size_t* bytes);
 
 /* Bytes of the workspace (reduction partials, reduction log, two-pass
- * pseudopotential field, read-out scratch).  Pure host computation. */
+ * pseudopotential field, read-out scratch, the link words of masked
+ * lattices).  Pure host computation. */
 int lbm_workspace_bytes(const lbm_config* cfg, size_t* bytes);
 
 /* Creates a handle on the current HIP device.  Validates the configuration and
@@ -202,13 +203,24 @@ int lbm_init_equilibrium(lbm_lattice* h, const double* rho0_dev, const double* u
  * LBM_ERR_EOS_DOMAIN or LBM_ERR_NONFINITE after the copy. */
 int lbm_step(lbm_lattice* h, int64_t n, int32_t reduce_every, lbm_reduction* out_host, int64_t n_out);
 
-/* Launch tuning of the fused strip kernels (lattices without solid masks or
- * moving walls): rows each wavefront marches through (4 <= rows <= 4096; 0
- * restores the default chosen from the lattice size and precision).  The
- * tile kernel of other lattices does not use it.
+/* Launch tuning of the fused strip kernels (unmasked lattices, and masked
+ * ones on the masked strip march): rows each wavefront marches through
+ * (1 <= rows <= 4096; 0 restores the default chosen from the lattice size and
+ * precision).  The tile kernel does not use it.
  * The state does not depend on it; reductions may differ in the last bits,
  * since their partial sums are grouped by run. */
 int lbm_set_rows_per_wave(lbm_lattice* h, int32_t rows);
+
+/* Kernel of the fused step on lattices with a solid mask or moving walls whose
+ * width is a multiple of 64: 1 (default) the masked strip march (wavefronts
+ * march aligned 64-column strips, bounce-back chosen per link from a 16-bit
+ * link word per node that the library writes into the workspace before the
+ * first step), 0 the tile kernel (one node per thread, psi of a tile in LDS).
+ * Both compute the same node arithmetic (float storage: the same state
+ * bitwise; double storage: to a few ulp, where the compiler contracts a
+ * product and a sum differently).  Also resets the rows per wave to the
+ * default.  on not 0 or 1: LBM_ERR_INVALID_ARG. */
+int lbm_set_masked_strips(lbm_lattice* h, int32_t on);
 
 /* Steps taken since lbm_init_equilibrium / lbm_set_state. */
 int lbm_step_count(const lbm_lattice* h, int64_t* steps);

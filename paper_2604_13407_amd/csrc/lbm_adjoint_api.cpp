@@ -137,6 +137,7 @@ int lbm_adjoint_forward(lbm_lattice* h, const lbm_adjoint_cfg* a, const double* 
   if (!rho0 || !workspace) return fail(h, LBM_ERR_INVALID_ARG, "rho0 and workspace must be non-NULL");
   if (((uintptr_t)workspace & 255u) != 0) return fail(h, LBM_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   if (h->buf.wall_u) return fail(h, LBM_ERR_UNSUPPORTED, "the adjoint does not support moving walls");
+  begin_stepping(h);
   const AdjLayout L = adj_layout(&h->cfg, a);
   if (workspace_bytes < L.total) return fail(h, LBM_ERR_INVALID_ARG, "adjoint workspace too small");
   char* ws = (char*)workspace;
@@ -226,6 +227,7 @@ int lbm_adjoint_forward(lbm_lattice* h, const lbm_adjoint_cfg* a, const double* 
 int lbm_adjoint_backward(lbm_lattice* h, double* grad_rho0, double* grad_force, double* grad_G) {
   if (!h) return LBM_ERR_INVALID_ARG;
   if (!h->adj.ready) return fail(h, LBM_ERR_STATE, "lbm_adjoint_backward without a matching lbm_adjoint_forward");
+  begin_stepping(h);
   const lbm_adjoint_cfg& a = h->adj.cfg;
   const AdjLayout L = adj_layout(&h->cfg, &a);
   char* ws = h->adj.ws;

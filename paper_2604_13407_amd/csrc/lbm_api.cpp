@@ -52,6 +52,24 @@ bool fast_path(const lbm_lattice* h) {
 // that every step streams them from HBM.
 bool streams_from_hbm(const lbm_config* c) { return 2.0 * (double)state_bytes_of(c) > 256.0 * 1048576.0; }
 
+// Lattices with a solid mask or moving walls whose width is a multiple of 64
+// (and whose population arrays fit 32-bit byte offsets) take the masked strip
+// march unless the tile kernel was asked for (lbm_set_masked_strips).
+bool masked_march(const lbm_lattice* h) {
+  double bytes = (double)state_bytes_of(&h->cfg);
+  return h->cfg.kernel == LBM_KERNEL_FUSED && (h->buf.mask || h->buf.wall_u) && h->cfg.nx % 64 == 0 &&
+         bytes < 4294967040.0 && h->masked_strips;
+}
+
+// Whether the fused step marches aligned 64-column strips.
+bool aligned_march(const lbm_lattice* h) {
+  return masked_march(h) || pplbm::aligned_strips(h->cfg.nx, fast_path(h) ? 1 : 0);
+}
+
+void begin_stepping(lbm_lattice* h) {
+  if (h->static_ws) h->links_ok = false;
+}
+
 bool replay_writes_traj(const lbm_lattice* h) {
   // the aligned strip kernel, with 32-bit byte offsets into the trajectory
   return fast_path(h) && pplbm::aligned_strips(h->cfg.nx, 1) &&
@@ -72,6 +90,17 @@ hipError_t step_between(lbm_lattice* h, const void* f_in, void* f_out, int reduc
   L.fast = fast_path(h) ? 1 : 0;
   L.traj = traj;
   L.interleave = (h->cfg.precision == LBM_FP32_DEV && streams_from_hbm(&h->cfg)) ? 1 : 0;
+  L.masked = masked_march(h) ? 1 : 0;
+  L.links = h->links;
+  L.tile_list = h->tile_list;
+  L.tile_count = h->tile_count;
+  L.moving_partials = h->moving_partials;
+  if (L.masked && !h->links_ok) {
+    hipError_t e = pplbm::launch_links(h->prm, h->buf.mask, h->buf.wall_u ? 1 : 0, h->links, h->tile_flags,
+                                       h->tile_list, h->tile_count, h->stream);
+    if (e != hipSuccess) return e;
+    h->links_ok = true;
+  }
   return (h->cfg.precision == LBM_FP64) ? pplbm::launch_step<double>(h->prm, L, h->stream)
                                         : pplbm::launch_step<float>(h->prm, L, h->stream);
 }
@@ -81,9 +110,9 @@ int n_parts_of(const lbm_lattice* h) {
   if (h->cfg.kernel == LBM_KERNEL_TWO_PASS) return pplbm::two_pass_blocks(nx, ny);
   // the fused kernels, as launch_step picks them
   const bool fast = fast_path(h);
-  if (fast && (pplbm::aligned_strips(nx, 1) || h->cfg.precision == LBM_FP64)) {
+  if (aligned_march(h) || (fast && h->cfg.precision == LBM_FP64)) {
     int n_strips, n_segs;
-    pplbm::fused_shape(nx, ny, h->seg_len, pplbm::aligned_strips(nx, 1), &n_strips, &n_segs);
+    pplbm::fused_shape(nx, ny, h->seg_len, aligned_march(h), &n_strips, &n_segs);
     return n_strips * n_segs;
   }
   return pplbm::tile_blocks(nx, ny);
@@ -125,7 +154,7 @@ bool config_ok(const lbm_config* c, std::string& why) {
   return true;
 }
 
-constexpr int kMinSegLen = 4;
+constexpr int kMinSegLen = 1;
 
 // Float storage re-references every node to its current density every this
 // many steps by default.  Without it the references of a moving interface go
@@ -148,15 +177,18 @@ constexpr int64_t kDefaultRerefEvery = 1000;
 // 2048 x 16384, float: 8 rows 63.2k, 12 64.3k, 16 63.9k, 24 61.8k, 32 62.0k;
 // double: 4 rows 34.3k, 8 35.6k, 16 34.9k, 24 34.0k.  512 x 2048 (cache
 // resident), float: 8 rows 48.5k, 16 rows 42.2k; double: 16 rows 35.2k, 8
-// rows 33.4k.
+// rows 33.4k.  Lattices too small to fill the chip with 6-row runs take
+// shorter ones, down to one row per wavefront (which pulls 3 rows for the 1
+// it stores): the 256 x 256 masked oblique channel, float storage, 11.4 us
+// per step at 4 rows, 9.9 at 3, 8.5 at 2, 6.9 at 1.
 int default_seg_len(const lbm_lattice* h) {
   const int nx = h->cfg.nx, ny = std::max(h->cfg.ny, 1);
   int n_strips, n_segs;
-  const bool aligned = pplbm::aligned_strips(nx, fast_path(h) ? 1 : 0);
+  const bool aligned = aligned_march(h);
   const bool fp64 = h->cfg.precision == LBM_FP64;
   const long target = fp64 ? 1024 : 2560;
   const int cap = streams_from_hbm(&h->cfg) ? (fp64 ? 8 : 12) : 24;
-  for (int rows : {24, 16, 12, 8, 6}) {
+  for (int rows : {24, 16, 12, 8, 6, 4, 3, 2}) {
     if (rows > cap) continue;
     pplbm::fused_shape(nx, ny, rows, aligned, &n_strips, &n_segs);
     if ((long)n_strips * n_segs >= target) return std::min(rows, ny);
@@ -174,7 +206,7 @@ size_t max_parts_for(const lbm_config* c) {
 }
 
 struct Layout {
-  size_t partials, log, red_tmp, psi, total;
+  size_t partials, log, red_tmp, psi, links, tiles, moving_partials, total;
 };
 
 Layout layout_for(const lbm_config* c) {
@@ -188,6 +220,14 @@ Layout layout_for(const lbm_config* c) {
   off = align256(off + RED_COUNT * sizeof(double));
   L.psi = off;
   off = align256(off + (size_t)c->nx * c->ny * sizeof(double));
+  L.links = off;
+  off = align256(off + (size_t)c->nx * c->ny * sizeof(uint16_t));
+  // tile flags, tile list, count (masked lattices with moving walls)
+  const size_t n_tiles = (size_t)pplbm::tile_blocks(c->nx, c->ny);
+  L.tiles = off;
+  off = align256(off + (2 * n_tiles + 1) * sizeof(int));
+  L.moving_partials = off;
+  off = align256(off + n_tiles * RED_COUNT * sizeof(double));
   L.total = off;
   return L;
 }
@@ -304,7 +344,9 @@ int lbm_create_static(const lbm_config* cfg, const lbm_buffers* buf, void* hip_s
   }
   lbm_buffers b = *buf;
   b.workspace = ws;
-  return lbm_create(cfg, &b, hip_stream, out);
+  const int rc = lbm_create(cfg, &b, hip_stream, out);
+  if (rc == LBM_OK) (*out)->static_ws = true;
+  return rc;
 }
 
 int lbm_create(const lbm_config* cfg, const lbm_buffers* buf, void* hip_stream, lbm_lattice** out) {
@@ -367,6 +409,14 @@ int lbm_create(const lbm_config* cfg, const lbm_buffers* buf, void* hip_stream, 
   h->log = (double*)(ws + L.log);
   h->red_tmp = (double*)(ws + L.red_tmp);
   h->psi = (void*)(ws + L.psi);
+  h->links = (uint16_t*)(ws + L.links);
+  {
+    const size_t n_tiles = (size_t)pplbm::tile_blocks(cfg->nx, cfg->ny);
+    h->tile_flags = (unsigned*)(ws + L.tiles);
+    h->tile_list = (int*)(ws + L.tiles) + n_tiles;
+    h->tile_count = (int*)(ws + L.tiles) + 2 * n_tiles;
+  }
+  h->moving_partials = (double*)(ws + L.moving_partials);
   rebuild_params(h);
   *out = h;
   return LBM_OK;
@@ -483,6 +533,7 @@ int lbm_step(lbm_lattice* h, int64_t n, int32_t reduce_every, lbm_reduction* out
     return fail(h, LBM_ERR_INVALID_ARG, "more reduction records than log_capacity in one call");
   std::vector<int64_t> rec_steps;
   rec_steps.reserve((size_t)records);
+  begin_stepping(h);
   const int parts = n_parts_of(h);
   for (int64_t t = 0; t < n; ++t) {
     int64_t idx = h->steps + 1;
@@ -490,7 +541,9 @@ int lbm_step(lbm_lattice* h, int64_t n, int32_t reduce_every, lbm_reduction* out
     hipError_t e = step_between(h, state_ptr(h, h->cur), state_ptr(h, 1 - h->cur), reduce);
     if (e != hipSuccess) return hip_fail(h, e, "step launch");
     if (reduce) {
-      e = pplbm::launch_finalize(h->partials, parts, h->log + rec_steps.size() * RED_COUNT, h->stream);
+      const bool mv = masked_march(h) && h->buf.wall_u;
+      e = pplbm::launch_finalize(h->partials, parts, h->log + rec_steps.size() * RED_COUNT, h->stream,
+                                 mv ? h->moving_partials : nullptr, mv ? h->tile_count : nullptr);
       if (e != hipSuccess) return hip_fail(h, e, "reduction launch");
       rec_steps.push_back(idx);
     }
@@ -524,8 +577,16 @@ int lbm_set_rows_per_wave(lbm_lattice* h, int32_t rows) {
     h->seg_len = default_seg_len(h);
     return LBM_OK;
   }
-  if (rows < kMinSegLen || rows > 4096) return fail(h, LBM_ERR_INVALID_ARG, "rows per wave must be in [4, 4096]");
+  if (rows < kMinSegLen || rows > 4096) return fail(h, LBM_ERR_INVALID_ARG, "rows per wave must be in [1, 4096]");
   h->seg_len = rows;
+  return LBM_OK;
+}
+
+int lbm_set_masked_strips(lbm_lattice* h, int32_t on) {
+  if (!h) return LBM_ERR_INVALID_ARG;
+  if (on != 0 && on != 1) return fail(h, LBM_ERR_INVALID_ARG, "masked strips: 0 or 1");
+  h->masked_strips = on;
+  h->seg_len = default_seg_len(h);
   return LBM_OK;
 }
 

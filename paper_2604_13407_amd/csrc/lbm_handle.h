@@ -43,6 +43,21 @@ struct lbm_lattice {
   double* log = nullptr;
   double* red_tmp = nullptr;
   void* psi = nullptr;
+  // masked lattices on the masked strip march: the per-node link words (in
+  // the workspace), whether they have been written since the handle was
+  // created (a handle on the library's static workspace, which other handles
+  // share, writes them again at every call that steps), and whether the
+  // masked strip march is enabled (1, default) or the tile kernel is used (0)
+  uint16_t* links = nullptr;
+  // ... and, with moving walls, the tiles that hold nodes beside the walls
+  // (flags, list, count) and those tiles' reduction partials
+  unsigned* tile_flags = nullptr;
+  int* tile_list = nullptr;
+  int* tile_count = nullptr;
+  double* moving_partials = nullptr;
+  bool links_ok = false;
+  bool static_ws = false;
+  int masked_strips = 1;
   AdjointRecord adj;
   std::string err;
 };
@@ -62,6 +77,9 @@ bool config_ok(const lbm_config* c, std::string& why);
 hipError_t step_between(lbm_lattice* h, const void* f_in, void* f_out, int reduce, double* traj = nullptr);
 // Whether the step kernel can write the adjoint trajectory itself.
 bool replay_writes_traj(const lbm_lattice* h);
+// Called by every entry point that steps: a handle on the shared static
+// workspace writes its link words again before its first step.
+void begin_stepping(lbm_lattice* h);
 int n_parts_of(const lbm_lattice* h);
 void* state_ptr(lbm_lattice* h, int which);
 void fill_record(const double* v, int64_t step, lbm_reduction* r);

@@ -24,6 +24,13 @@ struct StepLaunch {
                       // aligned strip kernel only, without reductions; NULL otherwise
   int interleave;     // aligned strip kernel: the XCDs take successive runs of rows in turn (0: each XCD
                       // takes one contiguous band of runs)
+  int masked;         // fused, width a multiple of 64, solid mask or moving walls: the masked strip march
+  const uint16_t* links;  // masked strip march: the per-node link words ([ny][nx], launch_links)
+  // masked strip march with moving walls: the tiles holding nodes beside the
+  // walls (launch_links) and their reduction partials
+  const int* tile_list;
+  const int* tile_count;
+  double* moving_partials;
 };
 
 int two_pass_blocks(int nx, int ny);
@@ -45,10 +52,20 @@ template <class S>
 hipError_t launch_fields(const StepParams& p, const void* f, const uint8_t* mask, const double* wall_u, void* psi,
                          double* rho, double* ux, double* uy, double* fx, double* fy, double* psi_o,
                          double* partials, int reduce, hipStream_t s);
+// Link words of a masked lattice for the masked strip march (bit 0 solid
+// node, bits 1-8 pull source solid or beyond a wall, bit 9 moving-wall term).
+// With moving walls, also the list of the tile kernel's 32 x 8 tiles that hold
+// a fluid node beside a moving wall (in increasing tile index) and its count;
+// tile_flags, tile_list: one entry per tile.
+hipError_t launch_links(const StepParams& p, const uint8_t* mask, int moving, uint16_t* links, unsigned* tile_flags,
+                        int* tile_list, int* tile_count, hipStream_t s);
 // Float storage: the reference density of every node becomes its current
 // density (both population arrays hold the current state).
 hipError_t launch_reref(const StepParams& p, void* fa, void* fb, const uint8_t* mask, hipStream_t s);
-hipError_t launch_finalize(const double* partials, int n_parts, double* out, hipStream_t s);
+// Fixed-order sum of n_parts partials (and of *extra_count more at extra, when
+// extra is non-NULL) into out[RED_COUNT].
+hipError_t launch_finalize(const double* partials, int n_parts, double* out, hipStream_t s,
+                           const double* extra = nullptr, const int* extra_count = nullptr);
 
 // Size of the library-owned workspace of lbm_create_static handles, and its
 // address on the current device (resolved once per device).

@@ -14,6 +14,8 @@
 // finished by a fixed-order kernel, so results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "lbm_internal.h"
 #include "lbm_node.h"
 
@@ -290,6 +292,196 @@ __device__ inline const StepParams& kernarg_params() {
   return *(const StepParams*)kp;
 }
 
+// ------------------------------------------------------------------ link words
+//
+// Per-node 16-bit link word of a masked lattice, read by the masked strip
+// march in place of the mask: bit 0 the node is solid; bit i (1..8) the pull
+// source x - e_i is solid or lies beyond a wall (the population then comes
+// from the node's own opposite one); bit 9 moving walls are given and some
+// pull source is a solid node inside the box (the node takes the moving-wall
+// term).  Written from the mask and the periodicity.
+constexpr unsigned LINK_SOLID = 1u, LINK_MOVING = 1u << 9;
+
+__global__ __launch_bounds__(256) void links_kernel(StepParams p, const uint8_t* __restrict__ mask, int moving,
+                                                   uint16_t* __restrict__ links, unsigned* __restrict__ tile_flags) {
+  // one 32 x 8 block per tile of the tile kernel; the tile's flag records
+  // whether it holds a fluid node beside a moving wall
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  bool mv = false;
+  if (x < p.nx && y < p.ny) {
+    const size_t k = (size_t)y * p.nx + x;
+    unsigned w = (mask && mask[k]) ? LINK_SOLID : 0u;
+    for (int i = 1; i < 9; ++i) {
+      int xs, ys;
+      bool inside;
+      if (solid_at(p, mask, x - ex(i), y - ey(i), xs, ys, inside)) {
+        w |= 1u << i;
+        if (moving && inside) w |= LINK_MOVING;
+      }
+    }
+    links[k] = (uint16_t)w;
+    mv = (w & (LINK_MOVING | LINK_SOLID)) == LINK_MOVING;
+  }
+  const int any = __syncthreads_or(mv);
+  if (threadIdx.x == 0 && threadIdx.y == 0) tile_flags[blockIdx.y * gridDim.x + blockIdx.x] = any ? 1u : 0u;
+}
+
+// The flagged tiles, in increasing tile index (one block; a fixed order, so
+// the reduction over the tiles' partial sums is reproducible), and their count.
+__global__ __launch_bounds__(1024) void compact_tiles_kernel(int n_tiles, const unsigned* __restrict__ flags,
+                                                             int* __restrict__ list, int* __restrict__ count) {
+  __shared__ int scan[1024];
+  const int t = threadIdx.x;
+  int base = 0;
+  for (int b0 = 0; b0 < n_tiles; b0 += 1024) {
+    const int f = (b0 + t < n_tiles && flags[b0 + t]) ? 1 : 0;
+    scan[t] = f;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int v = t >= off ? scan[t - off] : 0;
+      __syncthreads();
+      scan[t] += v;
+      __syncthreads();
+    }
+    if (f) list[base + scan[t] - 1] = b0 + t;
+    base += scan[1023];
+    __syncthreads();
+  }
+  if (t == 0) *count = base;
+}
+
+// pull_node for the tile step of nodes beside moving walls (ONLY_MOVING):
+// the same arithmetic, in the same order, but the solid links come from the
+// node's link word and every load (the node's own populations, the pulled
+// ones, the reference offsets of the pullers, the wall velocities at the 8
+// pull sources) is issued before any is used, so a node costs one memory
+// round trip instead of one per moving-wall link.
+template <class S>
+__device__ inline void pull_links(const StepParams& p, const S* __restrict__ f, const uint16_t* __restrict__ links,
+                                  const double* __restrict__ wall_u, int x, int y, double d[9], double* wall,
+                                  double& c, float* cdst) {
+  const int nx = p.nx;
+  const size_t plane = (size_t)nx * p.ny;
+  int xs[9], ys[9];
+  bool ins[9];
+  xs[0] = x;
+  ys[0] = y;
+  ins[0] = true;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    // the wrapped pull source x - e_i, as solid_at gives it
+    int xx = x - ex(i), yy = y - ey(i);
+    bool in = true;
+    if (xx < 0) {
+      in = in && p.periodic_x;
+      xx += nx;
+    } else if (xx >= nx) {
+      in = in && p.periodic_x;
+      xx -= nx;
+    }
+    if (yy < 0) {
+      in = in && p.periodic_y;
+      yy += p.ny;
+    } else if (yy >= p.ny) {
+      in = in && p.periodic_y;
+      yy -= p.ny;
+    }
+    xs[i] = xx;
+    ys[i] = yy;
+    ins[i] = in;
+  }
+  const unsigned lw = links[(size_t)y * nx + x];
+  double own[9], pulled[9], cref[9], uw[9], vw[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) own[q] = (double)f[pop_at<S>(nx, y, q, x)];
+#pragma unroll
+  for (int i = 1; i < 9; ++i) pulled[i] = (double)f[pop_at<S>(nx, ys[i], i, xs[i])];
+  const double c_self = ref_offset<S>(f, nx, y, x);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    // offset of the node that pulls population i from x: x + e_i, the pull
+    // source of direction opp(i)
+    const int j = opp(i);
+    cref[i] = i == 0 ? c_self : ref_offset<S>(f, nx, ys[j], xs[j]);
+  }
+  if (wall_u) {
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      const size_t ks = (size_t)ys[i] * nx + xs[i];
+      uw[i] = wall_u[ks];
+      vw[i] = wall_u[plane + ks];
+    }
+  }
+  c = c_self;
+  bool sol[9];
+  sol[0] = false;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) sol[i] = (lw >> i) & 1u;
+  double cd[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    cd[i] = 0.0;
+    if constexpr (sizeof(S) == 4) {
+      cd[i] = sol[opp(i)] ? c_self : cref[i];
+      if (cdst) cdst[i] = (float)cd[i];
+    }
+  }
+  double rho_w = 0.0;
+  if (wall_u) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) s += own[q] + wgt(q) * cd[q];
+    rho_w = p.rho_ref + s;
+  }
+  d[0] = own[0];
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    double v = sol[i] ? own[opp(i)] : pulled[i];
+    if (sol[i]) {
+      double mw = 0.0;
+      if (wall_u && ins[i]) {
+        const double eu = ex(i) * uw[i] + ey(i) * vw[i];
+        mw = 6.0 * wgt(i) * rho_w * eu;
+        v += mw;
+      }
+      if (wall) {
+        double fi = v + wgt(i) * (p.rho_ref + c_self);
+        double both = 2.0 * fi - mw;
+        wall[0] -= ex(i) * both;
+        wall[1] -= ey(i) * both;
+      }
+    }
+    d[i] = v;
+  }
+}
+
+// tile_psi_at from the link words (the pull of pull_links).
+template <class S>
+__device__ inline double tile_psi_links(const StepParams& p, const S* __restrict__ f,
+                                        const uint16_t* __restrict__ links, const double* __restrict__ wall_u,
+                                        int x, int y) {
+  if (x < -1 || x > p.nx || y < -1 || y > p.ny) return p.psi_solid;
+  int xw = x, yw = y;
+  bool inside = true;
+  if (xw < 0 || xw >= p.nx) {
+    inside = inside && p.periodic_x;
+    xw = xw < 0 ? xw + p.nx : xw - p.nx;
+  }
+  if (yw < 0 || yw >= p.ny) {
+    inside = inside && p.periodic_y;
+    yw = yw < 0 ? yw + p.ny : yw - p.ny;
+  }
+  if (!inside) return p.psi_solid;
+  double d[9], c;
+  pull_links<S>(p, f, links, wall_u, xw, yw, d, nullptr, c, nullptr);
+  if (links[(size_t)yw * p.nx + xw] & LINK_SOLID) return p.psi_solid;
+  double drho, jx, jy;
+  node_sums<S>(d, c, drho, jx, jy);
+  bool bad;
+  return psi_of(p, p.rho_ref + drho, bad);
+}
+
 // ------------------------------------------------------------------ fused tile kernel
 //
 // The fused step for every lattice the strip kernels do not take (solid
@@ -341,37 +533,55 @@ __device__ inline double tile_psi_at(const StepParams& p, const S* __restrict__ 
 
 int tile_blocks(int nx, int ny) { return ((nx + TILE_X - 1) / TILE_X) * ((ny + TILE_Y - 1) / TILE_Y); }
 
-template <class S, bool REDUCE>
-__global__ __launch_bounds__(256) void tile_kernel(StepParams p, const S* __restrict__ f, S* __restrict__ fo,
-                                                   const uint8_t* __restrict__ mask,
-                                                   const double* __restrict__ wall_u, double* __restrict__ partials) {
+// The tile step of the 32 x 8 tile at (x0, y0); `part` receives the tile's
+// reduction partial (REDUCE).  ONLY_MOVING: the step of the nodes beside
+// moving walls of a masked lattice on the masked strip march, run before the
+// march on the tiles that hold such nodes (fluid nodes whose link word has
+// LINK_MOVING): the whole tile step, but only those nodes are stored and
+// reduced, and their psi goes to `psi_moving`, where the march reads it for
+// their neighbours (the march skips them).
+template <class S, bool REDUCE, bool ONLY_MOVING>
+__device__ inline void tile_step(const StepParams& p, const S* __restrict__ f, S* __restrict__ fo,
+                                 const uint8_t* __restrict__ mask, const double* __restrict__ wall_u,
+                                 const uint16_t* __restrict__ links, double* __restrict__ psi_moving, int x0, int y0,
+                                 double* __restrict__ part) {
   __shared__ double lpsi[TILE_HY][TILE_HX];
   const int tx = threadIdx.x, ty = threadIdx.y;
-  const int x0 = blockIdx.x * TILE_X, y0 = blockIdx.y * TILE_Y;
   const int x = x0 + tx, y = y0 + ty;
   const bool active = x < p.nx && y < p.ny;
   const size_t k = active ? (size_t)y * p.nx + x : 0;
-  const bool fluid = active && !(mask && mask[k]);
+  bool moving = false, fluid;
+  if (ONLY_MOVING) {
+    const unsigned w = active ? links[k] : LINK_SOLID;
+    moving = (w & (LINK_MOVING | LINK_SOLID)) == LINK_MOVING;
+    fluid = active && !(w & LINK_SOLID);
+  } else {
+    fluid = active && !(mask && mask[k]);
+  }
   double d[9], c = 0.0, drho = 0.0, jx = 0.0, jy = 0.0;
   float cd[9];
   double wall[2] = {0.0, 0.0};
   bool bad = false;
   double ps = p.psi_solid;
   if (fluid) {
-    pull_node<S>(p, f, mask, wall_u, x, y, d, REDUCE ? wall : nullptr, c, sizeof(S) == 4 ? cd : nullptr);
+    if (ONLY_MOVING)
+      pull_links<S>(p, f, links, wall_u, x, y, d, REDUCE ? wall : nullptr, c, sizeof(S) == 4 ? cd : nullptr);
+    else
+      pull_node<S>(p, f, mask, wall_u, x, y, d, REDUCE ? wall : nullptr, c, sizeof(S) == 4 ? cd : nullptr);
     node_sums<S>(d, c, drho, jx, jy);
     ps = psi_of(p, p.rho_ref + drho, bad);
   } else if (!active) {
     // a tile position past the box's last column or row: the wrapped node, or
     // beyond a wall
-    ps = tile_psi_at<S>(p, f, mask, wall_u, x, y);
+    ps = ONLY_MOVING ? tile_psi_links<S>(p, f, links, wall_u, x, y) : tile_psi_at<S>(p, f, mask, wall_u, x, y);
   }
   lpsi[ty + 1][tx + 1] = ps;
   const int tid = ty * TILE_X + tx;
   if (tid < TILE_RING) {
     int hx, hy;
     tile_ring_pos(tid, hx, hy);
-    lpsi[hy][hx] = tile_psi_at<S>(p, f, mask, wall_u, x0 - 1 + hx, y0 - 1 + hy);
+    lpsi[hy][hx] = ONLY_MOVING ? tile_psi_links<S>(p, f, links, wall_u, x0 - 1 + hx, y0 - 1 + hy)
+                               : tile_psi_at<S>(p, f, mask, wall_u, x0 - 1 + hx, y0 - 1 + hy);
   }
   __syncthreads();
 
@@ -379,7 +589,8 @@ __global__ __launch_bounds__(256) void tile_kernel(StepParams p, const S* __rest
   double acc[RED_COUNT];
 #pragma unroll
   for (int q = 0; q < RED_COUNT; ++q) acc[q] = 0.0;
-  if (fluid) {
+  if (fluid && (!ONLY_MOVING || moving)) {
+    if (ONLY_MOVING) psi_moving[k] = ps;
     double Sx, Sy;
     stencil_sums(lpsi[ty + 1][tx + 2], lpsi[ty + 2][tx + 1], lpsi[ty + 1][tx], lpsi[ty][tx + 1], lpsi[ty + 2][tx + 2],
                  lpsi[ty + 2][tx], lpsi[ty][tx], lpsi[ty][tx + 2], Sx, Sy);
@@ -393,7 +604,36 @@ __global__ __launch_bounds__(256) void tile_kernel(StepParams p, const S* __rest
       accumulate_node(pc, acc, pc.rho_ref + drho, jx, jy, mac, bad);
     }
   }
-  if (REDUCE) block_reduce_store(acc, partials, blockIdx.y * gridDim.x + blockIdx.x);
+  if (REDUCE) block_reduce_store(acc, part, 0);
+}
+
+template <class S, bool REDUCE>
+__global__ __launch_bounds__(256) void tile_kernel(StepParams p, const S* __restrict__ f, S* __restrict__ fo,
+                                                   const uint8_t* __restrict__ mask,
+                                                   const double* __restrict__ wall_u, double* __restrict__ partials) {
+  tile_step<S, REDUCE, false>(p, f, fo, mask, wall_u, nullptr, nullptr, blockIdx.x * TILE_X, blockIdx.y * TILE_Y,
+                              partials + (size_t)(blockIdx.y * gridDim.x + blockIdx.x) * RED_COUNT);
+}
+
+// The tile step of the nodes beside moving walls, over the listed tiles (each
+// block takes tiles i, i + gridDim.x, ... of the list; tile i's partial is
+// partial i).
+template <class S, bool REDUCE>
+__global__ __launch_bounds__(256) void moving_tiles_kernel(StepParams p, const S* __restrict__ f, S* __restrict__ fo,
+                                                           const uint8_t* __restrict__ mask,
+                                                           const double* __restrict__ wall_u,
+                                                           const uint16_t* __restrict__ links,
+                                                           double* __restrict__ psi_moving,
+                                                           const int* __restrict__ list, const int* __restrict__ count,
+                                                           int tiles_x, double* __restrict__ partials) {
+  const int n = *count;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const int id = list[i];
+    const int ty0 = id / tiles_x, tx0 = id - ty0 * tiles_x;
+    tile_step<S, REDUCE, true>(p, f, fo, mask, wall_u, links, psi_moving, tx0 * TILE_X, ty0 * TILE_Y,
+                               partials + (size_t)i * RED_COUNT);
+    __syncthreads();  // the tile's psi in LDS is read before the next tile writes it
+  }
 }
 
 // ------------------------------------------------------------------ fast strip kernel
@@ -631,7 +871,6 @@ __device__ inline void march_row(const StepParams& p, const March& m, int y, con
   stencil_sums(pE, t1.psi, pW, tm.psi, pNE, pNW, pSW, pSE, Sx, Sy);
   NodeMacro mac = collide_node<S>(p, d, 0.0, t0.drho, t0.jx, t0.jy, t0.psi, Sx, Sy);
   const bool store = m.owner && t0.g.real;
-  const unsigned k = t0.g.own + m.c.own;
 #pragma unroll
   for (int i = 0; i < 9; ++i)
     BufIO<S>::store((S)d[i], m.out,
@@ -677,7 +916,6 @@ __device__ inline void march_row4(const StepParams& p, const March& m, int y, co
   stencil_sums(pE, t1.psi, pW, tm.psi, pNE, pNW, pSW, pSE, Sx, Sy);
   NodeMacro mac = collide_node<S>(p, d, 0.0, t0.drho, t0.jx, t0.jy, t0.psi, Sx, Sy);
   const bool store = m.owner && t0.g.real;
-  const unsigned k = t0.g.own + m.c.own;
 #pragma unroll
   for (int i = 0; i < 9; ++i)
     BufIO<S>::store((S)d[i], m.out,
@@ -866,6 +1104,14 @@ struct AMarch {
   // (the lane's own where there is none)
   unsigned href;
   double* traj;  // replay: rho - rho_ref, j_x, j_y, psi of every stored node, [4][ny][nx]
+  // masked lattices: the per-node link words, the psi of the nodes beside
+  // moving walls (written by moving_kernel before the march; NULL without
+  // moving walls), the population the lane pulls of a column beside the
+  // strip, and the column whose link word the lane reads for that column
+  // (x0-1 on lanes 0-8, x0+64 on lanes 48-56 and 63, its own elsewhere)
+  const uint16_t* links;
+  const double* psi_moving;
+  unsigned hidx, hlcol;
 };
 
 // Reference offsets of one row (float storage): c at the lane's column (m)
@@ -874,11 +1120,25 @@ struct RefRow {
   float m, h;
 };
 
+// Link words (masked lattices) of one row, packed in one register: the lane's
+// node (low half) and the column beside the strip (high half; see
+// AMarch::hlcol).
+struct LinkPair {
+  unsigned w;
+  __device__ unsigned own() const { return w & 0xFFFFu; }
+  __device__ unsigned halo() const { return w >> 16; }
+};
+
 template <class S>
 struct ASlot {
   S raw[9];  // the lane's 9 pulled populations (stored values)
   S rh;      // lanes 0-8 and 55-63: one population of a column beside the strip
   RefRow r;   // float storage: the reference offsets of this row
+  LinkPair lk;  // masked lattices: the link words the row was pulled with
+  // masked lattices with moving walls: psi of the lane's node and (lanes 0
+  // and 63) of the column beside the strip where that node takes the
+  // moving-wall term (moving_kernel computed it; 0 elsewhere)
+  double pm, ph;
 };
 
 struct ARow {
@@ -892,11 +1152,39 @@ struct ARow {
   RefRow cr;  // float storage: the reference offsets of this row
 };
 
-template <class S, bool INTERIOR>
-__device__ inline void aissue_row(const StepParams& p, const AMarch& m, int y, bool live, ASlot<S>& sl, RowGeo& g) {
+// Link words of row y (masked lattices); rows beyond a non-periodic edge read
+// row 0 (they are not pulled).
+__device__ inline LinkPair aload_links(const StepParams& p, const AMarch& m, int y) {
+  const RowGeo g = row_geo(p, y);
+  const unsigned row = g.real ? g.own : 0u;
+  const __amdgpu_buffer_rsrc_t r = buf_rsrc(m.links, 2u * m.N);
+  const unsigned own = (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, (int)(m.c.own * 2u), (int)(row * 2u), 0);
+  const unsigned halo = (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, (int)(m.hlcol * 2u), (int)(row * 2u), 0);
+  LinkPair lk;
+  lk.w = own | (halo << 16);
+  return lk;
+}
+
+template <class S, bool INTERIOR, bool MASKED, bool MOVING>
+__device__ inline void aissue_row(const StepParams& p, const AMarch& m, int y, bool live, ASlot<S>& sl, RowGeo& g,
+                                  const LinkPair& lk) {
   g = row_geo(p, y);
   const __amdgpu_buffer_rsrc_t in = buf_rsrc(m.f, live ? m.bytes : 0u);
-  if (INTERIOR) {
+  if (MASKED) {
+    // bounce-back wherever the link word says the pull source is solid or
+    // beyond a wall: the node's own opposite population
+    sl.lk = lk;
+    const unsigned own = state_planes<S>() * g.own + m.c.own;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const int exi = ex(i), eyi = ey(i);
+      const unsigned row = eyi == 1 ? g.bot : (eyi == -1 ? g.top : g.own);
+      const unsigned col = exi == 1 ? m.c.left : (exi == -1 ? m.c.right : m.c.own);
+      const bool wall = i > 0 && ((lk.own() >> i) & 1u);
+      const unsigned e = wall ? (unsigned)opp(i) * m.nx + own : state_planes<S>() * row + (unsigned)i * m.nx + col;
+      sl.raw[i] = BufIO<S>::load(in, g.real ? e * (unsigned)sizeof(S) : m.bytes);
+    }
+  } else if (INTERIOR) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const int eyi = ey(i);
@@ -909,7 +1197,27 @@ __device__ inline void aissue_row(const StepParams& p, const AMarch& m, int y, b
     pull_offsets<S>(g, m.c, m.nx, m.bytes, off);
     load_row<S>(in, off, sl.raw);
   }
-  {
+  if (MOVING) {
+    // psi of nodes beside moving walls (lanes whose node, or on lanes 0 and
+    // 63 the column beside the strip, takes the moving-wall term; the other
+    // lanes' offsets fall outside the buffer)
+    const __amdgpu_buffer_rsrc_t pr = buf_rsrc(m.psi_moving, (live && g.real) ? 8u * m.N : 0u);
+    const bool mo = (lk.own() & (LINK_MOVING | LINK_SOLID)) == LINK_MOVING;
+    const bool mh = m.h.real && (lk.halo() & (LINK_MOVING | LINK_SOLID)) == LINK_MOVING;
+    sl.pm = BufIO<double>::load(pr, mo ? (g.own + m.c.own) * 8u : 8u * m.N);
+    sl.ph = BufIO<double>::load(pr, mh ? (g.own + m.h.own) * 8u : 8u * m.N);
+  }
+  if (MASKED) {
+    // the columns beside the strip, one population per lane; the choices
+    // between rows and between pull and bounce-back are taken with bit masks
+    // (as selects, the compiler may turn the per-lane row choice into a table
+    // in scratch memory behind a branch)
+    const unsigned mb = 0u - (unsigned)(m.hey == 1), mt = 0u - (unsigned)(m.hey == -1);
+    const unsigned row = (g.bot & mb) | (g.top & mt) | (g.own & ~(mb | mt));
+    const unsigned mw = 0u - ((lk.halo() >> m.hidx) & (unsigned)(m.hidx > 0u));
+    const unsigned e = ((state_planes<S>() * g.own + m.hback) & mw) | ((state_planes<S>() * row + m.hplane + m.hcol) & ~mw);
+    sl.rh = BufIO<S>::load(in, (m.hon && g.real) ? e * (unsigned)sizeof(S) : m.bytes);
+  } else {
     // the columns beside the strip, one population per lane
     const unsigned row = m.hey == 1 ? g.bot : (m.hey == -1 ? g.top : g.own);
     const bool wall = !INTERIOR && (m.hwall || (m.hey == 1 && g.wall_b) || (m.hey == -1 && g.wall_t));
@@ -938,24 +1246,27 @@ __device__ inline float fbits_dpp(float v, float fill) {
 
 // Reference offsets of the nodes that pull row q's post-collision
 // populations, from the reference rows q-1 (`rb`), q (`r0`) and q+1 (`rt`):
-// cd[i] = c(x + e_i), or c(x) when x + e_i lies beyond a wall.  Lane 0's west
-// and lane 63's east neighbours are the columns beside the strip.
-template <bool INTERIOR>
+// cd[i] = c(x + e_i), or c(x) when x + e_i is solid or lies beyond a wall
+// (masked lattices: bit opp(i) of the node's link word).  Lane 0's west and
+// lane 63's east neighbours are the columns beside the strip.
+template <bool INTERIOR, bool MASKED>
 __device__ inline void dest_refs_row(const AMarch& m, const RowGeo& g, const RefRow& rb, const RefRow& r0,
-                                     const RefRow& rt, float cd[9]) {
-  const float cm[3] = {rb.m, r0.m, rt.m}, ch[3] = {rb.h, r0.h, rt.h};
-  float cw[3], ce[3];
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    cw[j] = fbits_dpp<0x138>(cm[j], ch[j]);  // x - 1 (lane 0: column x0-1)
-    ce[j] = fbits_dpp<0x130>(cm[j], ch[j]);  // x + 1 (lane 63: column x0+64)
-  }
+                                     const RefRow& rt, unsigned lkown, float cd[9]) {
+  // rows q-1, q, q+1 (b, 0, t) at columns x - 1 (w), x, x + 1 (e); lane 0's
+  // x - 1 and lane 63's x + 1 are the columns beside the strip (named values,
+  // not arrays, so that nothing is indexed at run time)
+  const float wb = fbits_dpp<0x138>(rb.m, rb.h), w0 = fbits_dpp<0x138>(r0.m, r0.h), wt = fbits_dpp<0x138>(rt.m, rt.h);
+  const float eb = fbits_dpp<0x130>(rb.m, rb.h), e0 = fbits_dpp<0x130>(r0.m, r0.h), et = fbits_dpp<0x130>(rt.m, rt.h);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const int exi = ex(i), eyi = ey(i);
-    const int j = 1 + eyi;
-    const float dst = exi == 1 ? ce[j] : (exi == -1 ? cw[j] : cm[j]);
-    if (INTERIOR) {
+    const float cw = eyi == 1 ? wt : (eyi == -1 ? wb : w0);
+    const float ce = eyi == 1 ? et : (eyi == -1 ? eb : e0);
+    const float cc = eyi == 1 ? rt.m : (eyi == -1 ? rb.m : r0.m);
+    const float dst = exi == 1 ? ce : (exi == -1 ? cw : cc);
+    if (MASKED) {
+      cd[i] = (i > 0 && ((lkown >> opp(i)) & 1u)) ? r0.m : dst;
+    } else if (INTERIOR) {
       cd[i] = dst;
     } else {
       const bool wall = (eyi == 1 && g.wall_t) || (eyi == -1 && g.wall_b) || (exi == 1 && m.c.wall_r) ||
@@ -1003,7 +1314,10 @@ __device__ inline double halo_sum(double v) {
   return row_dpp<0x11F>(a4);                   // lane 63: lane 48's sum; lane 0 keeps its own
 }
 
-template <class S>
+// Density, momentum and psi of a pulled row.  Masked lattices: psi_solid on
+// solid nodes; a node beside a moving wall (and a column beside the strip
+// whose node is one) takes the psi moving_kernel computed for it.
+template <class S, bool MASKED, bool MOVING>
 __device__ inline void arow_state(const StepParams& p, const AMarch& m, const ASlot<S>& sl, ARow& t) {
   double d[9];
 #pragma unroll
@@ -1014,30 +1328,42 @@ __device__ inline void arow_state(const StepParams& p, const AMarch& m, const AS
     ch = (double)sl.r.h;
     t.cr = sl.r;
   }
+  bool solid = false, hsolid = false, moving = false, hmoving = false;
+  if (MASKED) {
+    solid = (sl.lk.own() & LINK_SOLID) != 0u;
+    hsolid = (sl.lk.halo() & LINK_SOLID) != 0u;
+    if (MOVING) {
+      moving = !solid && (sl.lk.own() & LINK_MOVING);
+      hmoving = !hsolid && (sl.lk.halo() & LINK_MOVING);
+    }
+  }
   node_sums<S>(d, cm, t.drho, t.jx, t.jy);
   bool bad;
   const double ps = psi_of(p, p.rho_ref + t.drho, bad);
-  t.psi = t.g.real ? ps : p.psi_solid;
-  t.bad = t.g.real && bad;
+  t.psi = (t.g.real && !solid) ? (moving ? sl.pm : ps) : p.psi_solid;
+  t.bad = t.g.real && !solid && bad;
   // the halo column's density in the same arithmetic as its own strip uses
   double hr = halo_sum((double)sl.rh);
   if constexpr (sizeof(S) == 4) hr += ch;
   bool badh;
   const double psh = psi_of(p, p.rho_ref + hr, badh);
-  const double psih = (t.g.real && m.h.real) ? psh : p.psi_solid;
+  const double psih = (t.g.real && m.h.real && !hsolid) ? (hmoving ? sl.ph : psh) : p.psi_solid;
   t.pw = wave_shr1_fill(t.psi, psih);
   t.pe = wave_shl1_fill(t.psi, psih);
 }
 
 // Collide and store row y (slot `s0`, state `t0`), with psi of rows y-1 (`tm`)
 // and y+1 (`t1`, finished here from slot `s1`); the loads of row y + AHEAD
-// go into slot `sn` first.
-template <class S, bool REDUCE, bool TRAJ, bool INTERIOR, int AHEAD>
+// go into slot `sn` first.  Masked lattices: `ln` holds the link words of row
+// y + AHEAD, and the link words of row y + AHEAD + 1 are loaded into `l0`.
+template <class S, bool REDUCE, bool TRAJ, bool INTERIOR, bool MASKED, bool MOVING, int AHEAD>
 __device__ inline void amarch_row(const AMarch& m, int y, const ASlot<S>& s0, const ASlot<S>& s1, ASlot<S>& sn,
-                                  const ARow& tm, const ARow& t0, ARow& t1, ARow& tn, double* acc) {
+                                  const ARow& tm, const ARow& t0, ARow& t1, ARow& tn, LinkPair& l0,
+                                  const LinkPair& ln, double* acc) {
   const StepParams& p = kernarg_params();
-  aissue_row<S, INTERIOR>(p, m, y + AHEAD, y + AHEAD <= m.y1, sn, tn.g);
-  arow_state<S>(p, m, s1, t1);
+  if (MASKED) l0 = aload_links(p, m, y + AHEAD + 1);
+  aissue_row<S, INTERIOR, MASKED, MOVING>(p, m, y + AHEAD, y + AHEAD <= m.y1, sn, tn.g, ln);
+  arow_state<S, MASKED, MOVING>(p, m, s1, t1);
   const double pW = t0.pw, pE = t0.pe;
   const double pSW = tm.pw, pSE = tm.pe;
   const double pNW = t1.pw, pNE = t1.pe;
@@ -1046,6 +1372,10 @@ __device__ inline void amarch_row(const AMarch& m, int y, const ASlot<S>& s0, co
   for (int i = 0; i < 9; ++i) d[i] = (double)s0.raw[i];
   double cm = 0.0;
   if constexpr (sizeof(S) == 4) cm = (double)t0.cr.m;
+  // solid nodes keep their populations; nodes beside moving walls were
+  // collided and stored by moving_kernel
+  const bool skip = MASKED && ((s0.lk.own() & LINK_SOLID) || (MOVING && (s0.lk.own() & LINK_MOVING)));
+  const bool store = t0.g.real && !skip;
   double Sx, Sy;
   stencil_sums(pE, t1.psi, pW, tm.psi, pNE, pNW, pSW, pSE, Sx, Sy);
   double dw[9];
@@ -1054,16 +1384,17 @@ __device__ inline void amarch_row(const AMarch& m, int y, const ASlot<S>& s0, co
   NodeMacro mac = collide_node<S>(p, d, cm, t0.drho, t0.jx, t0.jy, t0.psi, Sx, Sy);
   float cd[9];
   if constexpr (sizeof(S) == 4) {
-    dest_refs_row<INTERIOR>(m, t0.g, tm.cr, t0.cr, t1.cr, cd);
+    dest_refs_row<INTERIOR, MASKED>(m, t0.g, tm.cr, t0.cr, t1.cr, MASKED ? s0.lk.own() : 0u, cd);
   } else {
 #pragma unroll
     for (int i = 0; i < 9; ++i) cd[i] = 0.0f;
   }
-  const bool store = t0.g.real;
-  const __amdgpu_buffer_rsrc_t out = buf_rsrc(m.fo, store ? m.bytes : 0u);
+  const __amdgpu_buffer_rsrc_t out = buf_rsrc(m.fo, t0.g.real ? m.bytes : 0u);
+  // a lane that does not store: its stores fall outside the buffer
+  const unsigned col = (!MASKED || store) ? m.c.own * (unsigned)sizeof(S) : m.bytes;
 #pragma unroll
   for (int i = 0; i < 9; ++i)
-    BufIO<S>::store(store_value<S>(d[i], wgt(i), (double)cd[i]), out, m.c.own * (unsigned)sizeof(S),
+    BufIO<S>::store(store_value<S>(d[i], wgt(i), (double)cd[i]), out, col,
                     (state_planes<S>() * t0.g.own + (unsigned)i * m.nx) * (unsigned)sizeof(S));
   if (TRAJ) {
     // the replayed step's pulled-state quantities, as the adjoint reads them
@@ -1078,10 +1409,15 @@ __device__ inline void amarch_row(const AMarch& m, int y, const ASlot<S>& s0, co
 #pragma unroll
       for (int i = 1; i < 9; ++i) {
         const int exi = ex(i), eyi = ey(i);
-        const bool wall = (eyi == 1 && t0.g.wall_b) || (eyi == -1 && t0.g.wall_t) || (exi == 1 && m.c.wall_l) ||
-                          (exi == -1 && m.c.wall_r);
+        bool wall;
+        if (MASKED)
+          wall = (s0.lk.own() >> i) & 1u;
+        else
+          wall = (eyi == 1 && t0.g.wall_b) || (eyi == -1 && t0.g.wall_t) || (exi == 1 && m.c.wall_l) ||
+                 (exi == -1 && m.c.wall_r);
         if (wall) {
-          // the pulled deviation at a wall link is the node's own opposite population
+          // the pulled deviation at a wall link is the node's own opposite
+          // population; the wall received -(f_i + fbar_opp) e_i = -2 f_i e_i
           double both = 2.0 * (dw[i] + wgt(i) * (p.rho_ref + cm));
           wx -= exi * both;
           wy -= eyi * both;
@@ -1096,23 +1432,33 @@ __device__ inline void amarch_row(const AMarch& m, int y, const ASlot<S>& s0, co
 
 // The march over rows y0 .. y1-1, with three row slots: row y+2 in flight
 // while row y collides.  (A fourth slot, rows y+2 and y+3 in flight, measured
-// the same or slower for both storages once runs are short.)
-template <class S, bool REDUCE, bool TRAJ, bool INTERIOR>
+// the same or slower for both storages once runs are short.)  Masked
+// lattices keep the link words one row further ahead, so that the offsets of
+// a row's pulls never wait for its link words.
+template <class S, bool REDUCE, bool TRAJ, bool INTERIOR, bool MASKED, bool MOVING>
 __device__ inline void amarch(const StepParams& p, const AMarch& m, int y0, double* acc) {
   ASlot<S> sa, sb, sc;
   ARow ta, tb, tc;
+  // link words of the next row each slot receives (masked lattices)
+  LinkPair la{0u}, lb{0u}, lc{0u};
+  if (MASKED) {
+    lc = aload_links(p, m, y0 - 1);
+    la = aload_links(p, m, y0);
+    lb = aload_links(p, m, y0 + 1);
+  }
   // row r lives in slot (r - y0 + 1) mod 3: y0-1 -> c, y0 -> a, y0+1 -> b
-  aissue_row<S, INTERIOR>(p, m, y0 - 1, true, sc, tc.g);
-  aissue_row<S, INTERIOR>(p, m, y0, true, sa, ta.g);
-  aissue_row<S, INTERIOR>(p, m, y0 + 1, true, sb, tb.g);
-  arow_state<S>(p, m, sc, tc);
-  arow_state<S>(p, m, sa, ta);
+  aissue_row<S, INTERIOR, MASKED, MOVING>(p, m, y0 - 1, true, sc, tc.g, lc);
+  aissue_row<S, INTERIOR, MASKED, MOVING>(p, m, y0, true, sa, ta.g, la);
+  aissue_row<S, INTERIOR, MASKED, MOVING>(p, m, y0 + 1, true, sb, tb.g, lb);
+  if (MASKED) lc = aload_links(p, m, y0 + 2);
+  arow_state<S, MASKED, MOVING>(p, m, sc, tc);
+  arow_state<S, MASKED, MOVING>(p, m, sa, ta);
   for (int y = y0; y < m.y1; y += 3) {
-    amarch_row<S, REDUCE, TRAJ, INTERIOR, 2>(m, y, sa, sb, sc, tc, ta, tb, tc, acc);
+    amarch_row<S, REDUCE, TRAJ, INTERIOR, MASKED, MOVING, 2>(m, y, sa, sb, sc, tc, ta, tb, tc, la, lc, acc);
     if (y + 1 >= m.y1) break;
-    amarch_row<S, REDUCE, TRAJ, INTERIOR, 2>(m, y + 1, sb, sc, sa, ta, tb, tc, ta, acc);
+    amarch_row<S, REDUCE, TRAJ, INTERIOR, MASKED, MOVING, 2>(m, y + 1, sb, sc, sa, ta, tb, tc, ta, lb, la, acc);
     if (y + 2 >= m.y1) break;
-    amarch_row<S, REDUCE, TRAJ, INTERIOR, 2>(m, y + 2, sc, sa, sb, tb, tc, ta, tb, acc);
+    amarch_row<S, REDUCE, TRAJ, INTERIOR, MASKED, MOVING, 2>(m, y + 2, sc, sa, sb, tb, tc, ta, tb, lc, lb, acc);
   }
 }
 
@@ -1145,11 +1491,12 @@ __device__ inline ColGeo col_geo(const StepParams& p, int x, bool want) {
   return c;
 }
 
-template <class S, bool REDUCE, bool TRAJ>
+template <class S, bool REDUCE, bool TRAJ, bool MASKED, bool MOVING>
 __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __restrict__ f, S* __restrict__ fo,
                                                       int n_strips, int seg_len, int n_segs, int groups, int per_xcd,
                                                       int interleave, double* __restrict__ partials,
-                                                      double* __restrict__ traj) {
+                                                      double* __restrict__ traj, const uint16_t* __restrict__ links,
+                                                      const double* __restrict__ psi_moving) {
   // Blocks go to the 8 XCDs round-robin (block b to XCD b mod 8).  Either
   // each XCD takes one contiguous band of runs, neighbouring runs sharing its
   // L2, or (interleave) the XCDs take successive runs in turn, so that all of
@@ -1197,11 +1544,18 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
     m.hey = ey(hi);
     m.hwall = (exi == 1 && hg.wall_l) || (exi == -1 && hg.wall_r);
     m.hon = (left || right) && hg.real;
+    m.hidx = (unsigned)hi;
+    // link word of the column beside the strip: the pulling lanes' column,
+    // and lane 63's (which takes that column's psi); the lane's own elsewhere
+    const ColGeo hr = col_geo(p, x0 + WAVE, true);
+    m.hlcol = (m.hon ? hg.own : ((lane == WAVE - 1 && hr.real) ? hr.own : m.c.own));
   }
   // float storage: byte offset within a row's reference run of the halo
   // column's offset (the lane's own where there is none)
   m.href = (m.h.real ? m.h.own : m.c.own) * 2u;
   m.traj = traj;
+  m.links = links;
+  m.psi_moving = psi_moving;
   const int y0 = seg * seg_len;
   m.y1 = min(y0 + seg_len, p.ny);
 
@@ -1212,10 +1566,12 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
   // Interior strips (the pulls of columns x0-1 .. x0+64 stay inside the box
   // without wrapping) of y-periodic lattices take the select-free offsets.
   const bool interior = p.periodic_y && x0 >= 2 && x0 + WAVE + 1 <= p.nx - 1;
-  if (interior)
-    amarch<S, REDUCE, TRAJ, true>(p, m, y0, acc);
+  if (MASKED)
+    amarch<S, REDUCE, TRAJ, false, true, MOVING>(p, m, y0, acc);
+  else if (interior)
+    amarch<S, REDUCE, TRAJ, true, false, false>(p, m, y0, acc);
   else
-    amarch<S, REDUCE, TRAJ, false>(p, m, y0, acc);
+    amarch<S, REDUCE, TRAJ, false, false, false>(p, m, y0, acc);
 
   if (REDUCE) {
 #pragma unroll
@@ -1227,7 +1583,10 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
 }
 
 // ------------------------------------------------------------------ finalize
-__global__ void finalize_kernel(const double* __restrict__ partials, int n_parts, double* __restrict__ out) {
+// Sum of the partials, then of the `*extra_count` partials at `extra` (the
+// tiles of nodes beside moving walls; NULL: none), in a fixed order.
+__global__ void finalize_kernel(const double* __restrict__ partials, int n_parts, const double* __restrict__ extra,
+                                const int* __restrict__ extra_count, double* __restrict__ out) {
   __shared__ double lds[RED_COUNT][256];
   const int t = threadIdx.x;
   double s[RED_COUNT];
@@ -1236,6 +1595,13 @@ __global__ void finalize_kernel(const double* __restrict__ partials, int n_parts
   for (int b = t; b < n_parts; b += 256) {
 #pragma unroll
     for (int q = 0; q < RED_COUNT; ++q) s[q] += partials[(size_t)b * RED_COUNT + q];
+  }
+  if (extra) {
+    const int ne = *extra_count;
+    for (int b = t; b < ne; b += 256) {
+#pragma unroll
+      for (int q = 0; q < RED_COUNT; ++q) s[q] += extra[(size_t)b * RED_COUNT + q];
+    }
   }
 #pragma unroll
   for (int q = 0; q < RED_COUNT; ++q) lds[q][t] = s[q];
@@ -1302,7 +1668,7 @@ hipError_t launch_step(const StepParams& p, const StepLaunch& L, hipStream_t st)
   const S* f = (const S*)L.f_in;
   S* fo = (S*)L.f_out;
   // only the aligned strip kernel writes the trajectory
-  if (L.traj && !(L.kernel == 0 && aligned_strips(p.nx, L.fast))) return hipErrorNotSupported;
+  if (L.traj && !(L.kernel == 0 && aligned_strips(p.nx, L.fast) && !L.masked)) return hipErrorNotSupported;
   if (L.kernel == 1) {
     dim3 blk(64, 4);
     dim3 grd = node_grid(p, blk);
@@ -1313,7 +1679,7 @@ hipError_t launch_step(const StepParams& p, const StepLaunch& L, hipStream_t st)
     else
       hipLaunchKernelGGL((collide_kernel<S, false>), grd, blk, 0, st, p, f, fo, L.mask, L.wall_u,
                          (const double*)L.psi, L.partials);
-  } else if (aligned_strips(p.nx, L.fast)) {
+  } else if (aligned_strips(p.nx, L.fast) || L.masked) {
     int n_strips, n_segs;
     fused_shape(p.nx, p.ny, L.seg_len, true, &n_strips, &n_segs);
     int groups = (n_strips + 3) / 4;
@@ -1321,16 +1687,47 @@ hipError_t launch_step(const StepParams& p, const StepLaunch& L, hipStream_t st)
     // blocks per XCD: interleaved, every strip group of ceil(n_segs / 8) runs
     int per_xcd = L.interleave ? groups * ((n_segs + 7) / 8) : (total + 7) / 8;
     const int il = L.interleave ? 1 : 0;
+    const dim3 grd(8 * per_xcd), blk(256);
     if (L.traj && L.reduce) return hipErrorInvalidValue;
-    if (L.traj)
-      hipLaunchKernelGGL((aligned_kernel<S, false, true>), dim3(8 * per_xcd), dim3(256), 0, st, p, f, fo, n_strips,
-                         L.seg_len, n_segs, groups, per_xcd, il, L.partials, L.traj);
+    if (L.masked) {
+      if (L.traj || p.nx % WAVE != 0 || !L.links) return hipErrorInvalidValue;
+      double* pm = nullptr;
+      if (L.wall_u) {
+        // the nodes beside moving walls first, on the tile kernel (their reduction
+        // partials follow the march's)
+        pm = (double*)L.psi;
+        const dim3 tblk(TILE_X, TILE_Y);
+        const int tiles_x = (p.nx + TILE_X - 1) / TILE_X;
+        const int n_tiles = tiles_x * ((p.ny + TILE_Y - 1) / TILE_Y);
+        const dim3 tgrd(std::min(n_tiles, 2048));
+        if (L.reduce)
+          hipLaunchKernelGGL((moving_tiles_kernel<S, true>), tgrd, tblk, 0, st, p, f, fo, L.mask, L.wall_u, L.links,
+                             pm, L.tile_list, L.tile_count, tiles_x, L.moving_partials);
+        else
+          hipLaunchKernelGGL((moving_tiles_kernel<S, false>), tgrd, tblk, 0, st, p, f, fo, L.mask, L.wall_u,
+                             L.links, pm, L.tile_list, L.tile_count, tiles_x, L.moving_partials);
+      }
+      if (pm && L.reduce)
+        hipLaunchKernelGGL((aligned_kernel<S, true, false, true, true>), grd, blk, 0, st, p, f, fo, n_strips,
+                           L.seg_len, n_segs, groups, per_xcd, il, L.partials, nullptr, L.links, pm);
+      else if (pm)
+        hipLaunchKernelGGL((aligned_kernel<S, false, false, true, true>), grd, blk, 0, st, p, f, fo, n_strips,
+                           L.seg_len, n_segs, groups, per_xcd, il, L.partials, nullptr, L.links, pm);
+      else if (L.reduce)
+        hipLaunchKernelGGL((aligned_kernel<S, true, false, true, false>), grd, blk, 0, st, p, f, fo, n_strips,
+                           L.seg_len, n_segs, groups, per_xcd, il, L.partials, nullptr, L.links, nullptr);
+      else
+        hipLaunchKernelGGL((aligned_kernel<S, false, false, true, false>), grd, blk, 0, st, p, f, fo, n_strips,
+                           L.seg_len, n_segs, groups, per_xcd, il, L.partials, nullptr, L.links, nullptr);
+    } else if (L.traj)
+      hipLaunchKernelGGL((aligned_kernel<S, false, true, false, false>), grd, blk, 0, st, p, f, fo, n_strips, L.seg_len,
+                         n_segs, groups, per_xcd, il, L.partials, L.traj, nullptr, nullptr);
     else if (L.reduce)
-      hipLaunchKernelGGL((aligned_kernel<S, true, false>), dim3(8 * per_xcd), dim3(256), 0, st, p, f, fo, n_strips,
-                         L.seg_len, n_segs, groups, per_xcd, il, L.partials, nullptr);
+      hipLaunchKernelGGL((aligned_kernel<S, true, false, false, false>), grd, blk, 0, st, p, f, fo, n_strips, L.seg_len,
+                         n_segs, groups, per_xcd, il, L.partials, nullptr, nullptr, nullptr);
     else
-      hipLaunchKernelGGL((aligned_kernel<S, false, false>), dim3(8 * per_xcd), dim3(256), 0, st, p, f, fo, n_strips,
-                         L.seg_len, n_segs, groups, per_xcd, il, L.partials, nullptr);
+      hipLaunchKernelGGL((aligned_kernel<S, false, false, false, false>), grd, blk, 0, st, p, f, fo, n_strips, L.seg_len,
+                         n_segs, groups, per_xcd, il, L.partials, nullptr, nullptr, nullptr);
   } else if (L.fast && launch_fast62<S>(p, L, st)) {
     // launched: the 62-column strip kernel (double storage, widths not a multiple of 64)
   } else {
@@ -1341,6 +1738,18 @@ hipError_t launch_step(const StepParams& p, const StepLaunch& L, hipStream_t st)
     else
       hipLaunchKernelGGL((tile_kernel<S, false>), grd, blk, 0, st, p, f, fo, L.mask, L.wall_u, L.partials);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_links(const StepParams& p, const uint8_t* mask, int moving, uint16_t* links, unsigned* tile_flags,
+                        int* tile_list, int* tile_count, hipStream_t st) {
+  const dim3 blk(TILE_X, TILE_Y);
+  const dim3 grd((p.nx + TILE_X - 1) / TILE_X, (p.ny + TILE_Y - 1) / TILE_Y);
+  hipLaunchKernelGGL(links_kernel, grd, blk, 0, st, p, mask, moving, links, tile_flags);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !moving) return e;
+  hipLaunchKernelGGL(compact_tiles_kernel, dim3(1), dim3(1024), 0, st, (int)(grd.x * grd.y), tile_flags, tile_list,
+                     tile_count);
   return hipGetLastError();
 }
 
@@ -1368,8 +1777,9 @@ hipError_t launch_fields(const StepParams& p, const void* f, const uint8_t* mask
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double* partials, int n_parts, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, partials, n_parts, out);
+hipError_t launch_finalize(const double* partials, int n_parts, double* out, hipStream_t s, const double* extra,
+                           const int* extra_count) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, partials, n_parts, extra, extra_count, out);
   return hipGetLastError();
 }
 

@@ -35,7 +35,7 @@ RED_FIELDS = ("mass", "mom_x", "mom_y", "wall_x", "wall_y", "uc_num", "uc_den", 
 EXPORTS = ("lbm_abi_version", "lbm_state_bytes", "lbm_workspace_bytes", "lbm_create", "lbm_destroy",
            "lbm_last_error", "lbm_set_eos", "lbm_set_G", "lbm_set_relaxation", "lbm_set_scheme",
            "lbm_set_body_force", "lbm_set_phase_densities", "lbm_set_walls", "lbm_init_equilibrium", "lbm_step",
-           "lbm_set_rows_per_wave",
+           "lbm_set_rows_per_wave", "lbm_set_masked_strips",
            "lbm_step_count", "lbm_read_fields", "lbm_reduce", "lbm_state_ptr", "lbm_get_state", "lbm_set_state",
            "lbm_rereference", "lbm_set_rereference_every", "lbm_adjoint_workspace_bytes", "lbm_adjoint_forward",
            "lbm_adjoint_backward", "lbm_create_static")
@@ -102,6 +102,7 @@ def lib():
         L.lbm_step.argtypes = [vp, C.c_int64, C.c_int32, C.POINTER(Reduction), C.c_int64]
         L.lbm_step_count.argtypes = [vp, C.POINTER(C.c_int64)]
         L.lbm_set_rows_per_wave.argtypes = [vp, C.c_int32]
+        L.lbm_set_masked_strips.argtypes = [vp, C.c_int32]
         L.lbm_read_fields.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.lbm_reduce.argtypes = [vp, C.POINTER(Reduction)]
         L.lbm_state_ptr.argtypes = [vp, C.POINTER(vp)]
@@ -225,6 +226,11 @@ class Lattice:
     def set_rows_per_wave(self, rows: int):
         """Launch tuning of the fused kernels (0 = default); results do not depend on it."""
         self._check(lib().lbm_set_rows_per_wave(self.h, rows), self.h)
+
+    def set_masked_strips(self, on: bool):
+        """Masked lattices of width a multiple of 64: the masked strip march (True,
+        default) or the tile kernel (False)."""
+        self._check(lib().lbm_set_masked_strips(self.h, 1 if on else 0), self.h)
 
     # ------------------------------------------------------------ state
     def init_equilibrium(self, rho0, ux0=None, uy0=None):

@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(LT.EXPORTS)
-    assert L.lbm_abi_version() == 3
+    assert L.lbm_abi_version() == 4
 
 
 def cfg(**kw):

@@ -91,6 +91,14 @@ def annulus_small():
                                             "r_liq_in": 35.0, "r_liq_out": 55.0})
 
 
+def annulus_aligned():
+    # width 192 (three 64-column strips): the masked strip march with a moving
+    # inner wall and a resting outer one
+    w = WL.annular_shear()
+    return w.with_size(192, 192, init_args={"centre": (95.5, 95.5), "r_in": 25.0, "r_out": 88.0, "u_wall": 0.01,
+                                            "r_liq_in": 40.0, "r_liq_out": 65.0})
+
+
 def droplet_small():
     # 130 columns = two full 62-column strips and a ragged one; walls in x
     w = WL.droplet()
@@ -125,6 +133,7 @@ CASES = [
     (droplet_aligned, 60),
     (periodic_aligned, 60),
     (channel_aligned, 200),
+    (annulus_aligned, 60),
 ]
 
 
@@ -151,7 +160,7 @@ def test_fp32_matches_oracle(case):
 
 
 @pytest.mark.parametrize("precision", [LT.FP64, LT.FP32_DEV])
-@pytest.mark.parametrize("case", [0, 2, 3, 4])
+@pytest.mark.parametrize("case", [0, 2, 3, 4, 9])
 def test_fused_and_two_pass_agree(case, precision):
     # Same node arithmetic in every kernel; the compiler may contract a*b+c into
     # an FMA differently in each, so FP64 states agree to a few ulp (FP32
@@ -307,7 +316,7 @@ def test_edge_shapes_fp32(nx, ny, px, py, use_mask):
 def test_rows_per_wave_do_not_change_results(precision, make):
     w = make()
     states, recs = [], []
-    for rows in (0, 4, 7, 24, 100):
+    for rows in (0, 1, 2, 4, 7, 24, 100):
         lat = LT.Lattice.from_workload(w, precision=precision)
         lat.set_rows_per_wave(rows)
         recs.append(lat.step(20, reduce_every=10))
