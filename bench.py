@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--adjoint-only", action="store_true", help="time only the adjoint (profiling)")
     ap.add_argument("--fp64-only", action="store_true", help="time only the FP64 path (profiling)")
+    ap.add_argument("--masked-only", action="store_true",
+                    help="time only the masked workloads, masked strip march and tile kernel (profiling)")
     ap.add_argument("--adjoint-steps", type=int, default=0,
                     help="steps of the adjoint run (default: the workload's 20,000)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -104,10 +106,12 @@ def warm_up(lat, warmup, reduce_every, min_s):
     return done
 
 
-def gpu_run(w, precision, steps, warmup, reduce_every, min_warmup_s=0.0, keep=False):
+def gpu_run(w, precision, steps, warmup, reduce_every, min_warmup_s=0.0, keep=False, tile=False):
     import torch
     from paper_2604_13407_amd import lattice as LT
     lat = LT.Lattice.from_workload(w, precision=precision, kernel=LT.KERNEL_FUSED)
+    if tile:
+        lat.set_masked_strips(False)
     warm = warm_up(lat, warmup, reduce_every, min_warmup_s)
     ms, wall = time_steps(lat, steps, reduce_every)
     rec = lat.reduce()
@@ -325,6 +329,24 @@ def accuracy_run(w, total, every, reref):
         del fa, fb
 
 
+def masked_workloads(steps, warmup, min_warmup_s):
+    """MLUPS of the masked workloads (solid masks; moving walls on the annulus) on
+    the masked strip march, the default, and beside it on the tile kernel.  These
+    lattices fit in the 256 MB last-level cache, so they are not HBM-bound."""
+    from paper_2604_13407_amd import lattice as LT
+    from paper_2604_13407_amd import workloads as WL
+    others, tiles = {}, {}
+    for name, make in (("oblique_poiseuille_256x256", WL.poiseuille_oblique),
+                       ("annular_shear_1024x1024", WL.annular_shear)):
+        wo = make()
+        for prec, tag in ((LT.FP32_DEV, "fp32"), (LT.FP64, "fp64")):
+            r = gpu_run(wo, prec, steps, warmup, 0, min_warmup_s)
+            others[f"{name}_{tag}"] = round(wo.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1)
+            r = gpu_run(wo, prec, steps, warmup, 0, min_warmup_s, tile=True)
+            tiles[f"{name}_{tag}"] = round(wo.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1)
+    return {"other_workloads_MLUPS": others, "other_workloads_tile_kernel_MLUPS": tiles}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -344,6 +366,9 @@ def main():
         return
     if args.accuracy_steps > 0:
         accuracy_run(w, args.accuracy_steps, args.accuracy_every, args.rereference_every)
+        return
+    if args.masked_only:
+        print(json.dumps(masked_workloads(steps, warmup, args.min_warmup_s)), flush=True)
         return
     if args.fp64_only:
         r = gpu_run(w, LT.FP64, steps, warmup, reduce_every, args.min_warmup_s)
@@ -404,16 +429,7 @@ def main():
                        args.min_warmup_s)
         result["original_scheme"] = {"value": round(w.nodes / (orig["ms_per_step"] * 1e-3) / 1e6, 1),
                                      "unit": "MLUPS", "ms_per_step": round(orig["ms_per_step"], 5)}
-        # the other workloads (general fused kernel: solid masks, moving walls); these
-        # lattices fit in the 256 MB last-level cache, so they are not HBM-bound
-        others = {}
-        for name, make in (("oblique_poiseuille_256x256", WL.poiseuille_oblique),
-                           ("annular_shear_1024x1024", WL.annular_shear)):
-            wo = make()
-            for prec, tag in ((LT.FP32_DEV, "fp32"), (LT.FP64, "fp64")):
-                r = gpu_run(wo, prec, steps, warmup, 0, args.min_warmup_s)
-                others[f"{name}_{tag}"] = round(wo.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1)
-        result["other_workloads_MLUPS"] = others
+        result.update(masked_workloads(steps, warmup, args.min_warmup_s))
         # the reductions and re-references a 200,000-step run of the workload makes, amortised
         result["amortised_costs_fp32"] = amortised_costs(w, LT.FP32_DEV)
         # the first steps after an idle spell (the power-management transient the warm-up skips)

@@ -1,17 +1,23 @@
 // HIP kernels of one pseudopotential MRT step for gfx950 (CDNA4, wave64).
 //
-// Two step implementations share the node arithmetic of lbm_node.h:
-//  * the fused strip kernel: one wavefront owns a 62-column strip (plus one
-//    halo column on each side) over a run of rows and marches up the rows.
-//    Each row is pulled once; its density and pseudopotential are computed
-//    in registers; the force stencil reads the three live rows of psi through
-//    cross-lane shuffles; the collision of the middle row is stored.  One
-//    kernel per step, populations read and written once (plus the halo).
+// Step implementations, all on the node arithmetic of lbm_node.h:
+//  * the aligned strip march (lattices whose width is a multiple of 64): a
+//    wavefront owns 64 aligned columns and marches up a run of rows; each row
+//    is pulled once, its density and pseudopotential are computed in
+//    registers, the x-neighbours' psi comes through DPP lane shifts and the
+//    y-neighbours' from the rows kept in registers, and the middle row is
+//    collided and stored as whole aligned lines.  Masked lattices (solid
+//    nodes, moving walls) take the same march with bounce-back chosen per link
+//    from a 16-bit link word per node; the nodes beside moving walls are
+//    stepped first by the tile kernel, on the tiles that hold them only;
+//  * the 62-column strip march (double storage, other widths);
+//  * the tile kernel (every other lattice): one node per thread, psi of a
+//    32 x 8 tile and its one-node ring in LDS;
 //  * the two-pass kernels: a psi pass writes the pseudopotential field, then
 //    a collide pass pulls again, reads psi of the 8 neighbours and collides.
-//    Simple, one node per thread; the reference for the fused kernel.
-// Reductions (every reduce_every steps) are FP64 per-wave partial sums
-// finished by a fixed-order kernel, so results are bitwise reproducible.
+//    Simple, one node per thread; the reference for the fused kernels.
+// Reductions (every reduce_every steps) are FP64 per-wave or per-block partial
+// sums finished by a fixed-order kernel, so results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
