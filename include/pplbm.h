@@ -141,7 +141,7 @@ int lbm_create(const lbm_config* cfg, const lbm_buffers* buf, void* hip_stream, 
  * LBM_STATIC_WORKSPACE_BYTES on the current device instead of a caller
  * buffer.  buf->workspace must be NULL; the caller still owns f_a, f_b, mask,
  * wall_u and every output.  Configurations whose lbm_workspace_bytes exceeds
- * LBM_STATIC_WORKSPACE_BYTES (about 4 million nodes) are rejected with
+ * LBM_STATIC_WORKSPACE_BYTES (about 2.8 million nodes) are rejected with
  * LBM_ERR_INVALID_ARG.  Allocates nothing: the array exists on every device
  * the library runs on until the process ends; its address is resolved the
  * first time this is called on a device.  Every handle made this way on one
