@@ -178,7 +178,8 @@ int lbm_adjoint_forward(lbm_lattice* h, const lbm_adjoint_cfg* a, const double* 
     e = step_between(h, state_ptr(h, h->cur), state_ptr(h, 1 - h->cur), reduce);
     if (e != hipSuccess) return hip_fail(h, e, "step launch");
     if (reduce) {
-      e = pplbm::launch_finalize(h->partials, n_parts_of(h), log + (size_t)(t - first_logged) * RED_COUNT, h->stream);
+      e = pplbm::launch_finalize(h->partials, n_parts_of(h), log + (size_t)(t - first_logged) * RED_COUNT,
+                                 h->fin_tmp, h->stream);
       if (e != hipSuccess) return hip_fail(h, e, "reduction launch");
     }
     h->cur = 1 - h->cur;

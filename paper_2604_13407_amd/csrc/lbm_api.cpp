@@ -206,7 +206,7 @@ size_t max_parts_for(const lbm_config* c) {
 }
 
 struct Layout {
-  size_t partials, log, red_tmp, psi, links, tiles, moving_partials, total;
+  size_t partials, log, red_tmp, fin_tmp, psi, links, tiles, moving_partials, total;
 };
 
 Layout layout_for(const lbm_config* c) {
@@ -218,6 +218,8 @@ Layout layout_for(const lbm_config* c) {
   off = align256(off + (size_t)c->log_capacity * RED_COUNT * sizeof(double));
   L.red_tmp = off;
   off = align256(off + RED_COUNT * sizeof(double));
+  L.fin_tmp = off;
+  off = align256(off + (size_t)pplbm::kFinalizeBlocks * RED_COUNT * sizeof(double));
   L.psi = off;
   off = align256(off + (size_t)c->nx * c->ny * sizeof(double));
   L.links = off;
@@ -408,6 +410,7 @@ int lbm_create(const lbm_config* cfg, const lbm_buffers* buf, void* hip_stream, 
   h->max_parts = max_parts_for(cfg);
   h->log = (double*)(ws + L.log);
   h->red_tmp = (double*)(ws + L.red_tmp);
+  h->fin_tmp = (double*)(ws + L.fin_tmp);
   h->psi = (void*)(ws + L.psi);
   h->links = (uint16_t*)(ws + L.links);
   {
@@ -542,7 +545,7 @@ int lbm_step(lbm_lattice* h, int64_t n, int32_t reduce_every, lbm_reduction* out
     if (e != hipSuccess) return hip_fail(h, e, "step launch");
     if (reduce) {
       const bool mv = masked_march(h) && h->buf.wall_u;
-      e = pplbm::launch_finalize(h->partials, parts, h->log + rec_steps.size() * RED_COUNT, h->stream,
+      e = pplbm::launch_finalize(h->partials, parts, h->log + rec_steps.size() * RED_COUNT, h->fin_tmp, h->stream,
                                  mv ? h->moving_partials : nullptr, mv ? h->tile_count : nullptr);
       if (e != hipSuccess) return hip_fail(h, e, "reduction launch");
       rec_steps.push_back(idx);
@@ -626,7 +629,8 @@ int lbm_reduce(lbm_lattice* h, lbm_reduction* out) {
                      : pplbm::launch_fields<float>(h->prm, f, h->buf.mask, h->buf.wall_u, h->psi, nullptr, nullptr,
                                                    nullptr, nullptr, nullptr, nullptr, h->partials, 1, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "fields launch");
-  e = pplbm::launch_finalize(h->partials, pplbm::two_pass_blocks(h->cfg.nx, h->cfg.ny), h->red_tmp, h->stream);
+  e = pplbm::launch_finalize(h->partials, pplbm::two_pass_blocks(h->cfg.nx, h->cfg.ny), h->red_tmp, h->fin_tmp,
+                             h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "reduction launch");
   double host[RED_COUNT];
   e = hipMemcpyAsync(host, h->red_tmp, sizeof host, hipMemcpyDeviceToHost, h->stream);

@@ -42,6 +42,7 @@ struct lbm_lattice {
   size_t max_parts = 0;
   double* log = nullptr;
   double* red_tmp = nullptr;
+  double* fin_tmp = nullptr;  // the reduction finish's first-stage sums
   void* psi = nullptr;
   // masked lattices on the masked strip march: the per-node link words (in
   // the workspace), whether they have been written since the handle was

@@ -63,8 +63,10 @@ hipError_t launch_links(const StepParams& p, const uint8_t* mask, int moving, ui
 // density (both population arrays hold the current state).
 hipError_t launch_reref(const StepParams& p, void* fa, void* fb, const uint8_t* mask, hipStream_t s);
 // Fixed-order sum of n_parts partials (and of *extra_count more at extra, when
-// extra is non-NULL) into out[RED_COUNT].
-hipError_t launch_finalize(const double* partials, int n_parts, double* out, hipStream_t s,
+// extra is non-NULL) into out[RED_COUNT], through tmp (kFinalizeBlocks *
+// RED_COUNT doubles).
+constexpr int kFinalizeBlocks = 128;
+hipError_t launch_finalize(const double* partials, int n_parts, double* out, double* tmp, hipStream_t s,
                            const double* extra = nullptr, const int* extra_count = nullptr);
 
 // Size of the library-owned workspace of lbm_create_static handles, and its

@@ -1589,26 +1589,17 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
 }
 
 // ------------------------------------------------------------------ finalize
-// Sum of the partials, then of the `*extra_count` partials at `extra` (the
-// tiles of nodes beside moving walls; NULL: none), in a fixed order.
-__global__ void finalize_kernel(const double* __restrict__ partials, int n_parts, const double* __restrict__ extra,
-                                const int* __restrict__ extra_count, double* __restrict__ out) {
+// Fixed-order sum of reduction partials in two stages.  Stage 1: block b of
+// FIN_BLOCKS sums the partials b, b + FIN_BLOCKS, ... of `partials` (then of
+// the `*extra_count` partials at `extra`, the tiles of nodes beside moving
+// walls, when extra is non-NULL) into tmp[b]; stage 2: one block sums the
+// FIN_BLOCKS results.  The grouping depends only on the counts, so the
+// result is bitwise reproducible.
+constexpr int FIN_BLOCKS = kFinalizeBlocks;
+
+__device__ inline void block_sum_to(double s[RED_COUNT], double* __restrict__ out) {
   __shared__ double lds[RED_COUNT][256];
   const int t = threadIdx.x;
-  double s[RED_COUNT];
-#pragma unroll
-  for (int q = 0; q < RED_COUNT; ++q) s[q] = 0.0;
-  for (int b = t; b < n_parts; b += 256) {
-#pragma unroll
-    for (int q = 0; q < RED_COUNT; ++q) s[q] += partials[(size_t)b * RED_COUNT + q];
-  }
-  if (extra) {
-    const int ne = *extra_count;
-    for (int b = t; b < ne; b += 256) {
-#pragma unroll
-      for (int q = 0; q < RED_COUNT; ++q) s[q] += extra[(size_t)b * RED_COUNT + q];
-    }
-  }
 #pragma unroll
   for (int q = 0; q < RED_COUNT; ++q) lds[q][t] = s[q];
   __syncthreads();
@@ -1620,6 +1611,37 @@ __global__ void finalize_kernel(const double* __restrict__ partials, int n_parts
     __syncthreads();
   }
   if (t < RED_COUNT) out[t] = lds[t][0];
+}
+
+__global__ __launch_bounds__(256) void finalize_stage1_kernel(const double* __restrict__ partials, int n_parts,
+                                                              const double* __restrict__ extra,
+                                                              const int* __restrict__ extra_count,
+                                                              double* __restrict__ tmp) {
+  const int t = threadIdx.x;
+  const int stride = FIN_BLOCKS * 256;
+  double s[RED_COUNT];
+#pragma unroll
+  for (int q = 0; q < RED_COUNT; ++q) s[q] = 0.0;
+  for (int b = blockIdx.x * 256 + t; b < n_parts; b += stride) {
+#pragma unroll
+    for (int q = 0; q < RED_COUNT; ++q) s[q] += partials[(size_t)b * RED_COUNT + q];
+  }
+  if (extra) {
+    const int ne = *extra_count;
+    for (int b = blockIdx.x * 256 + t; b < ne; b += stride) {
+#pragma unroll
+      for (int q = 0; q < RED_COUNT; ++q) s[q] += extra[(size_t)b * RED_COUNT + q];
+    }
+  }
+  block_sum_to(s, tmp + (size_t)blockIdx.x * RED_COUNT);
+}
+
+__global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ tmp, double* __restrict__ out) {
+  const int t = threadIdx.x;
+  double s[RED_COUNT];
+#pragma unroll
+  for (int q = 0; q < RED_COUNT; ++q) s[q] = t < FIN_BLOCKS ? tmp[(size_t)t * RED_COUNT + q] : 0.0;
+  block_sum_to(s, out);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1783,9 +1805,11 @@ hipError_t launch_fields(const StepParams& p, const void* f, const uint8_t* mask
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double* partials, int n_parts, double* out, hipStream_t s, const double* extra,
-                           const int* extra_count) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, partials, n_parts, extra, extra_count, out);
+hipError_t launch_finalize(const double* partials, int n_parts, double* out, double* tmp, hipStream_t s,
+                           const double* extra, const int* extra_count) {
+  hipLaunchKernelGGL(finalize_stage1_kernel, dim3(FIN_BLOCKS), dim3(256), 0, s, partials, n_parts, extra, extra_count,
+                     tmp);
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, tmp, out);
   return hipGetLastError();
 }
 
