@@ -253,10 +253,14 @@ def edge_case_run(nx, ny, px, py, use_mask, precision, steps=7):
     rng = np.random.default_rng(nx * 100 + ny)
     w = WL.small_droplet()
     w = w.with_size(nx, ny, periodic_x=px, periodic_y=py, init="none", perturb=0.05, seed=nx + ny)
-    mask = None
+    mask, wall_u = None, None
     if use_mask and nx * ny > 50:
         mask = (rng.random((ny, nx)) < 0.1).astype(np.uint8)
-    lat = LT.Lattice(nx, ny, px, py, precision, LT.KERNEL_FUSED, mask=mask)
+        if use_mask == "moving":
+            # every solid node moves with its own seeded velocity
+            wall_u = np.zeros((2, ny, nx))
+            wall_u[:, mask == 1] = rng.uniform(-0.02, 0.02, (2, int(mask.sum())))
+    lat = LT.Lattice(nx, ny, px, py, precision, LT.KERNEL_FUSED, mask=mask, wall_u=wall_u)
     lat.set_eos(w.eos_kind, w.a, w.b, w.R, w.T, w.k_eos)
     lat.set_relaxation(w.s)
     lat.set_scheme(w.scheme, w.eps)
@@ -271,7 +275,7 @@ def edge_case_run(nx, ny, px, py, use_mask, precision, steps=7):
     p = O.Params(nx=nx, ny=ny, periodic_x=px, periodic_y=py, eos_kind=w.eos_kind, T=w.T, eps=w.eps, s=w.s,
                  scheme=w.scheme, force_mode=O.FORCE_BUOYANT, fx=1e-6, fy=-2e-6, rho_g=w.rho_g, rho_l=w.rho_l,
                  rho_s=w.rho_s)
-    o = O.Oracle(p, mask=mask).init(rho0)
+    o = O.Oracle(p, mask=mask, wall_u=wall_u).init(rho0)
     o.step(steps)
     fl = np.ones((ny, nx), bool) if mask is None else mask == 0
     return g, o.macros(), fl
@@ -279,10 +283,13 @@ def edge_case_run(nx, ny, px, py, use_mask, precision, steps=7):
 
 EDGE_SHAPES = [
     (1, 1, True, True, True), (2, 3, True, True, True), (63, 17, False, False, True), (64, 5, True, False, True),
-    (125, 9, False, True, True), (200, 1, True, True, True),
+    (125, 9, False, True, True), (200, 1, True, True, True), (63, 17, False, False, "moving"),
     # without a mask these take the aligned 64-column kernel
     (64, 5, True, False, False), (128, 1, True, True, False), (64, 2, False, True, False),
-    (192, 7, False, False, False)]
+    (192, 7, False, False, False),
+    # with one, the masked strip march (rows and strips that wrap onto themselves; moving walls)
+    (64, 1, True, True, True), (64, 2, False, True, True), (128, 3, False, False, True),
+    (192, 7, True, False, "moving"), (64, 9, False, False, "moving"), (128, 4, True, True, "moving")]
 
 
 @pytest.mark.parametrize("nx,ny,px,py,use_mask", EDGE_SHAPES)
