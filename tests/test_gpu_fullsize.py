@@ -227,3 +227,34 @@ def test_oblique_full_run():
         scale_u = max(np.max(np.abs(g["ux"])), np.max(np.abs(g["uy"])), 1e-12)
         check(w, g, om, 0, w.nx, 0, w.ny, precision, scale_u, tol64=fp64_bar(w.steps))
         del lat
+
+
+def test_fp32_storage_holds_the_bars_over_the_stated_horizon():
+    """Float storage against the FP64 path on the full 2048 x 16384 falling
+    droplet over 60,000 steps, the longest run of that lattice whose pointwise
+    density difference stays within 1e-5 (every 10,000 steps: 0.8, 1.8, 2.6,
+    3.6, 5.9, 7.7 x 1e-6, then 1.3e-5 at 70,000; at a moving interface this bar
+    bounds how far the two droplets drift apart), with the default
+    re-reference every 1,000 steps; the velocity stays within 1e-4 of the peak
+    (the whole 200,000-step run keeps it)."""
+    w = WL.droplet()
+    steps = 60000
+    fields = {}
+    for precision in (LT.FP64, LT.FP32_DEV):
+        lat = LT.Lattice.from_workload(w, precision=precision)
+        for done in range(0, steps, 10000):
+            lat.step(10000)
+            torch.cuda.synchronize()
+            print(f"[horizon] precision={precision} {done + 10000} steps", flush=True)
+        f = lat.read_fields()
+        torch.cuda.synchronize()
+        fields[precision] = {k: f[k] for k in ("rho", "ux", "uy")}
+        del lat
+        torch.cuda.empty_cache()
+    a, b = fields[LT.FP32_DEV], fields[LT.FP64]
+    peak = torch.sqrt(b["ux"] ** 2 + b["uy"] ** 2).max().item()
+    du = torch.sqrt((a["ux"] - b["ux"]) ** 2 + (a["uy"] - b["uy"]) ** 2).max().item() / peak
+    drho = ((a["rho"] - b["rho"]).abs() / b["rho"]).max().item()
+    print(f"[horizon] {steps} steps: density {drho:.3e}, velocity {du:.3e} of the peak {peak:.3e}", flush=True)
+    assert drho <= 1e-5
+    assert du <= 1e-4
