@@ -91,6 +91,8 @@ hipError_t step_between(lbm_lattice* h, const void* f_in, void* f_out, int reduc
   L.traj = traj;
   L.interleave = (h->cfg.precision == LBM_FP32_DEV && streams_from_hbm(&h->cfg)) ? 1 : 0;
   L.masked = masked_march(h) ? 1 : 0;
+  // lattices that stream from HBM: the waves of a block march in lockstep
+  L.lockstep = streams_from_hbm(&h->cfg) ? 1 : 0;
   L.links = h->links;
   L.tile_list = h->tile_list;
   L.tile_count = h->tile_count;

@@ -31,6 +31,7 @@ struct StepLaunch {
   const int* tile_list;
   const int* tile_count;
   double* moving_partials;
+  int lockstep;       // aligned strip kernel (unmasked): the 4 waves of a block march in lockstep
 };
 
 int two_pass_blocks(int nx, int ny);
