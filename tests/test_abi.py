@@ -25,7 +25,9 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(LT.EXPORTS)
-    assert L.lbm_abi_version() == 4
+    with open(os.path.join(ROOT, "include", "pplbm.h")) as fh:
+        abi = int(re.search(r"#define LBM_ABI_VERSION (\d+)", fh.read()).group(1))
+    assert L.lbm_abi_version() == abi == 4
 
 
 def cfg(**kw):
