@@ -167,7 +167,7 @@ constexpr int kMinSegLen = 1;
 // re-reference costs about two steps' worth of memory traffic.
 constexpr int64_t kDefaultRerefEvery = 1000;
 
-// Rows each wavefront marches: the longest of 24, 16, 12, 8, 6 rows that
+// Rows each wavefront marches: the longest of 24, 16, 14, 12, 8, 6 rows that
 // still gives the launch enough wavefronts to fill the chip (2,560 for float
 // storage, which fits 3 per SIMD, 1,024 for double).  A run recomputes the
 // pseudopotential of the two rows beside it, so longer runs read and compute
@@ -175,11 +175,14 @@ constexpr int64_t kDefaultRerefEvery = 1000;
 // many runs at once.  Lattices whose two population arrays exceed the 256 MB
 // last-level cache stream from HBM, and there short runs are faster: the
 // waves resident at one time then read fewer, fuller DRAM rows.  Those take
-// at most 12 rows (float) or 8 (double).  Measured on gfx950 (MLUPS):
+// at most 14 rows (float) or 8 (double).  Measured on gfx950 (MLUPS):
 // 2048 x 16384, float: 8 rows 63.2k, 12 64.3k, 16 63.9k, 24 61.8k, 32 62.0k;
 // double: 4 rows 34.3k, 8 35.6k, 16 34.9k, 24 34.0k.  512 x 2048 (cache
 // resident), float: 8 rows 48.5k, 16 rows 42.2k; double: 16 rows 35.2k, 8
-// rows 33.4k.  Lattices too small to fill the chip with 6-row runs take
+// rows 33.4k.  With the waves of a block in lockstep (lattices that stream
+// from HBM), 2048 x 16384, ms per step, float: 12 rows 0.504, 14 0.502, 16
+// 0.503, 20 0.504; double: 8 rows 0.914, 10 0.918, 16 0.935.  Lattices too
+// small to fill the chip with 6-row runs take
 // shorter ones, down to one row per wavefront (which pulls 3 rows for the 1
 // it stores): the 256 x 256 masked oblique channel, float storage, 11.4 us
 // per step at 4 rows, 9.9 at 3, 8.5 at 2, 6.9 at 1.
@@ -189,8 +192,8 @@ int default_seg_len(const lbm_lattice* h) {
   const bool aligned = aligned_march(h);
   const bool fp64 = h->cfg.precision == LBM_FP64;
   const long target = fp64 ? 1024 : 2560;
-  const int cap = streams_from_hbm(&h->cfg) ? (fp64 ? 8 : 12) : 24;
-  for (int rows : {24, 16, 12, 8, 6, 4, 3, 2}) {
+  const int cap = streams_from_hbm(&h->cfg) ? (fp64 ? 8 : 14) : 24;
+  for (int rows : {24, 16, 14, 12, 8, 6, 4, 3, 2}) {
     if (rows > cap) continue;
     pplbm::fused_shape(nx, ny, rows, aligned, &n_strips, &n_segs);
     if ((long)n_strips * n_segs >= target) return std::min(rows, ny);
