@@ -283,3 +283,50 @@ def test_longer_horizon_droplet_against_the_oracle():
     assert rel(L, Lo) <= 1e-11
     assert rel(gG, dGo) <= 1e-9 and rel(gf, dgo) <= 1e-9
     assert rel(float((g * vs[0]).sum()), dvo[0]) <= 1e-9
+
+
+def aligned_masked_case():
+    """A masked lattice of width 64 (one strip: the forward and replay steps run on
+    the masked strip march), periodic in x, the original scheme."""
+    w = WL.small_droplet(nx=64, ny=32, radius=7.0, g=1e-5)
+    w = replace(w, periodic_x=True, scheme=WL.SCHEME_ORIGINAL)
+    mask = np.zeros((w.ny, w.nx), np.uint8)
+    mask[12:16, 3:7] = 1
+    mask[0:2, 50:53] = 1
+    mask[25, 63] = 1
+    return w, mask
+
+
+@pytest.mark.parametrize("precision", [LT.FP64, LT.FP32_DEV])
+def test_adjoint_on_the_masked_strip_march(precision):
+    # The adjoint's forward run and its replays take the masked strip march on
+    # this lattice: the gradients equal the tile kernel's (to the rounding of
+    # sums grouped differently) and, in FP64, the oracle's complex-step
+    # derivatives.
+    w, mask = aligned_masked_case()
+    kind = LT.LOSS_DRAG
+    outs = []
+    for masked in (True, False):
+        lat = lattice_for(w, precision, LT.KERNEL_FUSED, mask)
+        lat.set_masked_strips(masked)
+        L = lat.adjoint_forward(w.rho0(), N_SMALL, loss=kind, window=W_SMALL, checkpoint_every=K_SMALL)
+        g, gf, gG = lat.adjoint_backward()
+        torch.cuda.synchronize()
+        outs.append((L, gG, gf, g.cpu().numpy()))
+    (La, gGa, gfa, ga), (Lb, gGb, gfb, gb) = outs
+    if precision == LT.FP32_DEV:
+        # the replayed states are bitwise equal; the loss and the parameter
+        # gradients are sums grouped by the kernels' runs or tiles
+        assert rel(La, Lb) <= 1e-12 and rel(gGa, gGb) <= 1e-12 and rel(gfa, gfb) <= 1e-12
+        assert np.max(np.abs(ga - gb)) <= 1e-12 * np.max(np.abs(gb))
+    else:
+        assert rel(La, Lb) <= 1e-12 and rel(gGa, gGb) <= 1e-11 and rel(gfa, gfb) <= 1e-11
+        assert np.max(np.abs(ga - gb)) <= 1e-11 * np.max(np.abs(gb))
+        Lo, dGo, dgo, dvo = oracle_derivatives(w, mask, kind, None, N_SMALL, W_SMALL, directions(w, 1))
+        print(f"masked march adjoint: L {La:.6e} (oracle {Lo:.6e}) dG {gGa:.6e} ({dGo:.6e}) "
+              f"dg {gfa:.6e} ({dgo:.6e})", flush=True)
+        assert rel(La, Lo) <= 1e-11, (La, Lo)
+        assert rel(gGa, dGo) <= 1e-9 and rel(gfa, dgo) <= 1e-9
+        v = directions(w, 1)[0]
+        assert rel(float(np.sum(ga * v)), dvo[0]) <= 1e-9
+    assert np.all(ga[mask == 1] == 0.0)
