@@ -229,6 +229,21 @@ def small_droplet(nx: int = 48, ny: int = 64, radius: float = 10.0, scheme: int 
                    init_args={"centre": (nx / 2 - 0.5, ny / 2 - 0.5), "radius": radius}, perturb=perturb)
 
 
+def vdw_layer(nx: int = 64, ny: int = 96, key: str = "vdw_0.50_eps1.895", tau: float = 1.0, fx: float = 0.0,
+              periodic_y: bool = True, scheme: int = SCHEME_IMPROVED) -> Workload:
+    """A flat liquid layer, y in [ny/4, 3ny/4), in the van der Waals fluid of
+    Sec. 3 (a = 9/49, b = 2/21, R = 1, K = 1/16) at one of its coexistence
+    cases.  The default is the setting of Sec. 3.2 (T_r = 0.5, eps = 1.895,
+    density ratio about 113) in a box periodic in x and y; with
+    ``periodic_y=False`` and a force ``fx`` it is the aligned two-phase channel
+    of Sec. 3.1 (keys ``vdw_0.72_eps0``, ``vdw_0.65_eps1``, ``vdw_0.54_eps2``)."""
+    c = COEXISTENCE[key]
+    rg, rl = c["rho_g"], c["rho_l"]
+    return Workload(f"vdw_layer_{key}", nx, ny, True, periodic_y, EOS_VDW, 9.0 / 49.0, 2.0 / 21.0, 1.0, c["T"],
+                    1.0 / 16.0, c["eps"], rates_from_tau(tau), FORCE_CONST, fx, 0.0, rg, rl, rg, 0,
+                    scheme=scheme, init="layer_y", init_args={"y0": ny // 4, "y1": 3 * ny // 4})
+
+
 ALL = {
     "poiseuille_aligned": poiseuille_aligned,
     "poiseuille_oblique": poiseuille_oblique,

@@ -13,15 +13,22 @@ normal along y, so the paper's (x, y) become (y, x): its directions 2, 4 become
   second-order source terms through eps only.
 * Sec. 2.2: the improved scheme leaves a static interface unchanged.
 * Eq. (1): a converged flat interface sits near the eps-mechanical-stability
-  coexistence densities (the coexistence-curve check of Sec. 3.1).
+  coexistence densities (the coexistence-curve check of Sec. 3.1); at Sec.
+  3.2's setting (eps = 1.895, T_r = 0.5) on the Maxwell densities, ratio 113.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
 
 from oracle import coexistence as X
 from oracle import oracle as O
+from paper_2604_13407_amd import workloads as WL
+from tests.helpers import oracle_for
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_numbers.json")))
 
 
 def converge(o, chunk=2000, max_steps=400000, tol=1e-12, static=False):
@@ -191,6 +198,32 @@ def test_flat_interface_reaches_mechanical_stability_densities():
     assert abs(r[0] / rg - 1) < 2e-2
     assert abs(r[0] / mg - 1) > 0.5
     assert 55 < r[47] / r[0] < 65
+
+
+def test_flat_interface_at_the_annular_setting_is_thermodynamically_consistent():
+    # Sec. 3.2's van der Waals setting (T_r = 0.5, eps = 1.895): eps is chosen
+    # there so that the coexistence densities are the thermodynamic ones, with a
+    # density ratio of about 113.  A converged flat interface of the full step
+    # (Q_m with k1 = k2 = -eps/16) must land on the Maxwell equal-area densities
+    # (an independent closed form of the EOS) and on the paper's ratio; Eq. (1)'s
+    # continuum gas density at this eps lies 4% away, so the check separates the two.
+    g = GOLDEN["annular_density_ratio"]
+    eos = X.vdw_paper(g["T_r"])
+    mg, ml, _ = X.maxwell(eos)
+    rg, rl, _ = X.mechanical_stability(eos, g["eps"])
+    for scheme in (O.SCHEME_ORIGINAL, O.SCHEME_IMPROVED):
+        w = WL.vdw_layer(nx=2, ny=96, scheme=scheme)
+        assert w.T == eos.T and w.eps == g["eps"] and w.k_eos == eos.k_eos
+        o = oracle_for(w)
+        o.step(30000)
+        r = o.macros()["rho"][:, 0]
+        liq, gas = r[48], r[0]
+        print(f"[Sec. 3.2] scheme {scheme}: rho_l {liq:.6f} (Maxwell {ml:.6f}), rho_g {gas:.6f} "
+              f"(Maxwell {mg:.6f}, Eq. (1) {rg:.6f}), ratio {liq / gas:.3f} (paper {g['ratio']})")
+        assert abs(liq / ml - 1) < 1e-5 and abs(liq / rl - 1) < 1e-4
+        assert abs(gas / mg - 1) < 1e-3
+        assert abs(gas / rg - 1) > 0.03
+        assert abs(liq / gas - g["ratio"]) < 0.5
 
 
 def oblique(scheme, eps, tau, F, N=32, T_r=0.8):
