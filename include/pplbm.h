@@ -153,8 +153,10 @@ int lbm_create_static(const lbm_config* cfg, const lbm_buffers* buf, void* hip_s
 /* Releases the handle (not the caller's buffers).  NULL is accepted. */
 int lbm_destroy(lbm_lattice* h);
 
-/* Message of the last error on this handle ("" if none); with h = NULL, the
- * last error of lbm_create.  The pointer stays valid until the next call. */
+/* Message of the last error on this handle ("" if none); with h = NULL, that
+ * of the last call made without a handle (lbm_create, lbm_create_static,
+ * lbm_state_bytes, lbm_workspace_bytes, lbm_adjoint_workspace_bytes; each
+ * clears it first).  The pointer stays valid until the next such call. */
 const char* lbm_last_error(const lbm_lattice* h);
 
 /* Equation of state p_EOS(rho).  kind LBM_EOS_VDW: Eq. (43),

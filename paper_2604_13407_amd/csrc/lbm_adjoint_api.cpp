@@ -122,8 +122,10 @@ T* at(char* ws, size_t off) {
 extern "C" {
 
 int lbm_adjoint_workspace_bytes(const lbm_config* cfg, const lbm_adjoint_cfg* a, size_t* bytes) {
+  g_create_error.clear();
   std::string why;
-  if (!bytes || !config_ok(cfg, why) || !adj_cfg_ok(a, why)) return LBM_ERR_INVALID_ARG;
+  if (!bytes) return fail_query(LBM_ERR_INVALID_ARG, "bytes is NULL");
+  if (!config_ok(cfg, why) || !adj_cfg_ok(a, why)) return fail_query(LBM_ERR_INVALID_ARG, why);
   *bytes = adj_layout(cfg, a).total;
   return LBM_OK;
 }

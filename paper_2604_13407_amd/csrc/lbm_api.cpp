@@ -124,6 +124,11 @@ void* state_ptr(lbm_lattice* h, int which) { return which == 0 ? h->buf.f_a : h-
 
 std::string g_create_error;
 
+int fail_query(int code, const std::string& msg) {
+  g_create_error = msg;
+  return code;
+}
+
 bool config_ok(const lbm_config* c, std::string& why) {
   if (!c) {
     why = "config is NULL";
@@ -308,15 +313,19 @@ extern "C" {
 int lbm_abi_version(void) { return LBM_ABI_VERSION; }
 
 int lbm_state_bytes(const lbm_config* cfg, size_t* bytes) {
+  g_create_error.clear();
   std::string why;
-  if (!bytes || !config_ok(cfg, why)) return LBM_ERR_INVALID_ARG;
+  if (!bytes) return fail_query(LBM_ERR_INVALID_ARG, "bytes is NULL");
+  if (!config_ok(cfg, why)) return fail_query(LBM_ERR_INVALID_ARG, why);
   *bytes = state_bytes_of(cfg);
   return LBM_OK;
 }
 
 int lbm_workspace_bytes(const lbm_config* cfg, size_t* bytes) {
+  g_create_error.clear();
   std::string why;
-  if (!bytes || !config_ok(cfg, why)) return LBM_ERR_INVALID_ARG;
+  if (!bytes) return fail_query(LBM_ERR_INVALID_ARG, "bytes is NULL");
+  if (!config_ok(cfg, why)) return fail_query(LBM_ERR_INVALID_ARG, why);
   *bytes = layout_for(cfg).total;
   return LBM_OK;
 }

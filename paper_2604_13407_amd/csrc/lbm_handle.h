@@ -71,10 +71,15 @@ size_t state_bytes_of(const lbm_config* c);
 int fail(lbm_lattice* h, int code, const std::string& msg);
 int hip_fail(lbm_lattice* h, hipError_t e, const char* what);
 bool config_ok(const lbm_config* c, std::string& why);
+// Calls without a handle (lbm_create, lbm_create_static and the size queries)
+// keep their last message here; lbm_last_error(NULL) returns it.
+extern std::string g_create_error;
+// Records `msg` as the message of a call without a handle and returns `code`.
+int fail_query(int code, const std::string& msg);
 // One step from f_in to f_out with the handle's kernels and launch shape;
-// reduce = 1 writes reduction partials (n_parts_of(h) of them).
-// One step from f_in to f_out; `traj` (NULL, or [4][ny][nx] doubles: the
-// step's rho - rho_ref, j_x, j_y, psi) only where replay_writes_traj(h).
+// reduce = 1 writes reduction partials (n_parts_of(h) of them); `traj` (NULL,
+// or [4][ny][nx] doubles: the step's rho - rho_ref, j_x, j_y, psi) only where
+// replay_writes_traj(h).
 hipError_t step_between(lbm_lattice* h, const void* f_in, void* f_out, int reduce, double* traj = nullptr);
 // Whether the step kernel can write the adjoint trajectory itself.
 bool replay_writes_traj(const lbm_lattice* h);

@@ -313,7 +313,7 @@ class Lattice:
         acfg = AdjointConfig(int(n_steps), int(window), int(loss), int(checkpoint_every),
                              None if ut is None else ut.data_ptr())
         nb = C.c_size_t(0)
-        self._check(lib().lbm_adjoint_workspace_bytes(C.byref(self.cfg), C.byref(acfg), C.byref(nb)), self.h)
+        self._check(lib().lbm_adjoint_workspace_bytes(C.byref(self.cfg), C.byref(acfg), C.byref(nb)), None)
         ws = getattr(self, "_adj_ws", None)
         if ws is None or ws.numel() < nb.value:
             self._adj_ws = None

@@ -47,6 +47,14 @@ def test_sizes_and_config_validation():
     for bad in (dict(nx=0), dict(ny=-3), dict(precision=7), dict(kernel=5), dict(log_capacity=0),
                 dict(nx=100000, ny=100000), dict(rho_ref=math.inf)):
         assert L.lbm_state_bytes(C.byref(cfg(**bad)), C.byref(b)) == -1, bad
+        # a call without a handle leaves its message for lbm_last_error(NULL)
+        assert L.lbm_last_error(None).decode(), bad
+        assert L.lbm_workspace_bytes(C.byref(cfg(**bad)), C.byref(b)) == -1, bad
+        assert L.lbm_last_error(None).decode(), bad
+    assert L.lbm_workspace_bytes(C.byref(cfg()), None) == -1
+    assert "NULL" in L.lbm_last_error(None).decode()
+    # and a successful one clears it
+    assert L.lbm_workspace_bytes(C.byref(cfg()), C.byref(b)) == 0 and L.lbm_last_error(None).decode() == ""
 
 
 def fake_handle():
@@ -136,6 +144,9 @@ def test_adjoint_workspace_size_and_validation():
     for bad in (dict(n_steps=0), dict(checkpoint_every=0), dict(window=1), dict(window=101), dict(loss=7),
                 dict(loss=LT.LOSS_UERR)):
         assert L.lbm_adjoint_workspace_bytes(C.byref(c), C.byref(acfg(**bad)), C.byref(b)) == -1, bad
+        assert L.lbm_last_error(None).decode(), bad
+    assert L.lbm_adjoint_workspace_bytes(C.byref(c), C.byref(acfg(window=1)), C.byref(b)) == -1
+    assert "window" in L.lbm_last_error(None).decode()
     assert L.lbm_adjoint_workspace_bytes(C.byref(c), C.byref(acfg(loss=LT.LOSS_UERR, u_target_dev=0x1000)),
                                          C.byref(b)) == 0
 

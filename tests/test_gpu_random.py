@@ -133,3 +133,77 @@ def test_random_configuration_matches_oracle(seed):
                               ("uc_num", "uc_num", mom_scale), ("pphi", "pphi", mom_scale)):
             assert abs(r[kg] - ref[ko]) <= tol * max(abs(ref[ko]), scale), (seed, kg, r[kg], ref[ko])
         assert r["faults"] == ref["faults"] == 0
+
+
+N_ADJ = 24
+
+
+def draw_adjoint(seed):
+    """A small random adjoint case (node-steps kept within the oracle's tape)."""
+    rng = np.random.default_rng(5000 + seed)
+    nx = int(rng.choice([8, 13, 24, 64, 65, 128]))
+    ny = int(rng.choice([6, 9, 16, 24]))
+    n = int(rng.integers(4, 21))
+    while nx * ny * n > 25000:
+        n -= 1
+    c = dict(nx=nx, ny=ny, n=n, px=bool(rng.random() < 0.6), py=bool(rng.random() < 0.6),
+             scheme=int(rng.integers(0, 2)), precision=LT.FP64 if rng.random() < 0.5 else LT.FP32_DEV,
+             kernel=LT.KERNEL_TWO_PASS if rng.random() < 0.25 else LT.KERNEL_FUSED,
+             loss=LT.LOSS_UERR if rng.random() < 0.5 else LT.LOSS_DRAG,
+             window=int(rng.integers(2, n + 1)), k=int(rng.integers(1, n + 4)))
+    # the drag loss weighs the buoyant force; the velocity error takes either force
+    c["buoyant"] = c["loss"] == LT.LOSS_DRAG or bool(rng.random() < 0.5)
+    kind = str(rng.choice(["none", "scatter", "blobs"]))
+    mask = None
+    if kind == "scatter":
+        mask = (rng.random((ny, nx)) < 0.1).astype(np.uint8)
+    elif kind == "blobs":
+        mask = blobs(nx, ny, rng)
+    c.update(mask=mask, kind=kind, rho0=0.05 + 0.2 * rng.random((ny, nx)),
+             ut=rng.normal(size=(ny, nx)) * 1e-3 if c["loss"] == LT.LOSS_UERR else None)
+    return c
+
+
+@pytest.mark.parametrize("seed", range(N_ADJ))
+def test_random_adjoint_matches_the_oracle_adjoint(seed):
+    """dL/drho0 node by node, dL/dG and dL/d|F| of a random small case against the
+    oracle's own discrete adjoint: FP64 within 1e-9, float storage within 1e-3."""
+    c = draw_adjoint(seed)
+    nx, ny = c["nx"], c["ny"]
+    print(f"[random adjoint] seed={seed} {nx}x{ny} n={c['n']} px={c['px']} py={c['py']} mask={c['kind']} "
+          f"scheme={c['scheme']} buoyant={c['buoyant']} precision={c['precision']} kernel={c['kernel']} "
+          f"loss={c['loss']} window={c['window']} k={c['k']}", flush=True)
+    w = WL.small_droplet()
+    fmode = LT.FORCE_BUOYANT if c["buoyant"] else LT.FORCE_CONST
+    fx, fy = (0.0, -1e-5) if c["buoyant"] else (2e-6, 1e-6)
+    rho_ref = w.rho_g if c["precision"] == LT.FP32_DEV else 0.0
+    lat = LT.Lattice(nx, ny, c["px"], c["py"], c["precision"], c["kernel"], rho_ref, mask=c["mask"])
+    lat.set_eos(w.eos_kind, w.a, w.b, w.R, w.T, w.k_eos)
+    lat.set_relaxation(w.s)
+    lat.set_scheme(c["scheme"], w.eps)
+    lat.set_body_force(fmode, fx, fy)
+    lat.set_phase_densities(w.rho_g, w.rho_l)
+    lat.set_walls(w.rho_s)
+    L = lat.adjoint_forward(c["rho0"], c["n"], loss=c["loss"], window=c["window"], checkpoint_every=c["k"],
+                            u_target=c["ut"])
+    g, gF, gG = lat.adjoint_backward()
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+
+    p = O.Params(nx=nx, ny=ny, periodic_x=c["px"], periodic_y=c["py"], eos_kind=w.eos_kind, a=w.a, b=w.b, R=w.R,
+                 T=w.T, k_eos=w.k_eos, eps=w.eps, s=w.s, scheme=c["scheme"],
+                 force_mode=O.FORCE_BUOYANT if c["buoyant"] else O.FORCE_CONST, fx=fx, fy=fy,
+                 rho_g=w.rho_g, rho_l=w.rho_l, rho_s=w.rho_s)
+    Lo, go, dGo, dFo = O.adjoint(p, c["rho0"], c["n"], c["loss"], window=c["window"], u_target=c["ut"],
+                                 mask=c["mask"])
+    tol = 1e-9 if c["precision"] == LT.FP64 else 1e-3
+    err = np.max(np.abs(g - go)) / np.max(np.abs(go))
+    rl = abs(L - Lo) / abs(Lo)
+    rG = abs(gG - dGo) / max(abs(dGo), 1e-300)
+    rF = abs(gF - dFo) / max(abs(dFo), 1e-300)
+    print(f"[random adjoint] L {rl:.2e} field {err:.2e} dG {rG:.2e} dF {rF:.2e}", flush=True)
+    assert rl <= (1e-11 if c["precision"] == LT.FP64 else 1e-3), (seed, "L", rl)
+    assert err <= tol, (seed, "field", err)
+    assert rG <= tol and rF <= tol, (seed, rG, rF)
+    if c["mask"] is not None:
+        assert np.all(g[c["mask"] == 1] == 0.0)
