@@ -303,12 +303,20 @@ def test_checkpoint_resume_is_bitwise(precision, make):
     assert torch.equal(a.state(), b.state())
 
 
-def test_runs_are_deterministic():
-    w = WL.poiseuille_oblique()
+@pytest.mark.parametrize("make,precision,every", [
+    (lambda: WL.poiseuille_oblique(), LT.FP32_DEV, 10),
+    # masked strip march with moving walls: the listed tiles' partials follow the march's
+    (annulus_aligned, LT.FP64, 1), (annulus_aligned, LT.FP32_DEV, 3),
+    # the tile kernel with a moving wall, and aligned strips with walls
+    (annulus_small, LT.FP64, 2), (droplet_aligned, LT.FP64, 1)])
+def test_runs_are_deterministic(make, precision, every):
+    # two runs of the same configuration: the same state and the same reduction
+    # records, bit for bit (every reduction is a fixed-order sum)
+    w = make()
     outs = []
     for _ in range(2):
-        lat = LT.Lattice.from_workload(w, precision=LT.FP32_DEV)
-        recs = lat.step(30, reduce_every=10)
+        lat = LT.Lattice.from_workload(w, precision=precision)
+        recs = lat.step(30, reduce_every=every)
         torch.cuda.synchronize()
         outs.append((lat.state().clone(), recs))
     assert torch.equal(outs[0][0], outs[1][0])
