@@ -213,9 +213,11 @@ int lbm_step(lbm_lattice* h, int64_t n, int32_t reduce_every, lbm_reduction* out
  * since their partial sums are grouped by run. */
 int lbm_set_rows_per_wave(lbm_lattice* h, int32_t rows);
 
-/* Kernel of the fused step on lattices with a solid mask or moving walls whose
- * width is a multiple of 64: 1 (default) the masked strip march (wavefronts
- * march aligned 64-column strips, bounce-back chosen per link from a 16-bit
+/* Kernel of the fused step on lattices with a solid mask or moving walls (of
+ * any width with float storage; double storage: widths that are a multiple of
+ * 64, or lattices whose two population arrays exceed 256 MB): 1 (default) the
+ * masked strip march (wavefronts march aligned 64-column strips, the last one
+ * partial where the width is not a multiple of 64, bounce-back chosen per link from a 16-bit
  * link word per node that the library writes into the workspace before the
  * first step), 0 the tile kernel (one node per thread, psi of a tile in LDS).
  * Both compute the same node arithmetic (float storage: the same state

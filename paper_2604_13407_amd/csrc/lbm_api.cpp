@@ -52,19 +52,29 @@ bool fast_path(const lbm_lattice* h) {
 // that every step streams them from HBM.
 bool streams_from_hbm(const lbm_config* c) { return 2.0 * (double)state_bytes_of(c) > 256.0 * 1048576.0; }
 
-// Lattices with a solid mask or moving walls whose width is a multiple of 64
-// (and whose population arrays fit 32-bit byte offsets) take the masked strip
-// march unless the tile kernel was asked for (lbm_set_masked_strips).
-bool masked_march(const lbm_lattice* h) {
-  double bytes = (double)state_bytes_of(&h->cfg);
-  return h->cfg.kernel == LBM_KERNEL_FUSED && (h->buf.mask || h->buf.wall_u) && h->cfg.nx % 64 == 0 &&
-         bytes < 4294967040.0 && h->masked_strips;
+// Widths that are not a multiple of 64 end in a partial strip.  The strip
+// march takes them for float storage (1.6-2.8x the tile kernel: 1000 x 1000
+// droplet 22.4k -> 41.9k MLUPS, 2000 x 4096 20.3k -> 56.2k, 1000 x 1000 annulus
+// with moving walls 16.6k -> 26.6k) and for lattices that stream from HBM
+// (double storage, 2000 x 4096: the 62-column kernel 30.8k, the march 34.7k).
+// Double storage on lattices that sit in the last-level cache keeps the
+// 62-column kernel (1000 x 1000 droplet: 29.5k against 27.3k) or the tile
+// kernel (the annulus: 24.5k against 21.8k).
+bool strip_width_ok(const lbm_lattice* h) {
+  return h->cfg.nx % 64 == 0 || h->cfg.precision == LBM_FP32_DEV || streams_from_hbm(&h->cfg);
 }
 
-// Whether the fused step marches aligned 64-column strips.
-bool aligned_march(const lbm_lattice* h) {
-  return masked_march(h) || pplbm::aligned_strips(h->cfg.nx, fast_path(h) ? 1 : 0);
+// Lattices with a solid mask or moving walls (whose population arrays fit
+// 32-bit byte offsets) take the masked strip march unless the tile kernel was
+// asked for (lbm_set_masked_strips).
+bool masked_march(const lbm_lattice* h) {
+  double bytes = (double)state_bytes_of(&h->cfg);
+  return h->cfg.kernel == LBM_KERNEL_FUSED && (h->buf.mask || h->buf.wall_u) && bytes < 4294967040.0 &&
+         h->masked_strips && strip_width_ok(h);
 }
+
+// Whether the fused step marches 64-column strips.
+bool aligned_march(const lbm_lattice* h) { return masked_march(h) || (fast_path(h) && strip_width_ok(h)); }
 
 void begin_stepping(lbm_lattice* h) {
   if (h->static_ws) h->links_ok = false;
@@ -72,7 +82,7 @@ void begin_stepping(lbm_lattice* h) {
 
 bool replay_writes_traj(const lbm_lattice* h) {
   // the aligned strip kernel, with 32-bit byte offsets into the trajectory
-  return fast_path(h) && pplbm::aligned_strips(h->cfg.nx, 1) &&
+  return fast_path(h) && strip_width_ok(h) &&
          32.0 * (double)h->cfg.nx * (double)h->cfg.ny < 4294967040.0;
 }
 
@@ -91,6 +101,7 @@ hipError_t step_between(lbm_lattice* h, const void* f_in, void* f_out, int reduc
   L.traj = traj;
   L.interleave = (h->cfg.precision == LBM_FP32_DEV && streams_from_hbm(&h->cfg)) ? 1 : 0;
   L.masked = masked_march(h) ? 1 : 0;
+  L.aligned = (!L.masked && aligned_march(h)) ? 1 : 0;
   // lattices that stream from HBM: the waves of a block march in lockstep
   L.lockstep = streams_from_hbm(&h->cfg) ? 1 : 0;
   L.links = h->links;

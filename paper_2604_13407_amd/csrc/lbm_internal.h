@@ -24,7 +24,9 @@ struct StepLaunch {
                       // aligned strip kernel only, without reductions; NULL otherwise
   int interleave;     // aligned strip kernel: the XCDs take successive runs of rows in turn (0: each XCD
                       // takes one contiguous band of runs)
-  int masked;         // fused, width a multiple of 64, solid mask or moving walls: the masked strip march
+  int aligned;        // fused, no mask or moving walls: the strip march over 64-column strips (the last
+                      // one partial where the width is not a multiple of 64)
+  int masked;         // fused, solid mask or moving walls: the masked strip march
   const uint16_t* links;  // masked strip march: the per-node link words ([ny][nx], launch_links)
   // masked strip march with moving walls: the tiles holding nodes beside the
   // walls (launch_links) and their reduction partials
@@ -38,10 +40,9 @@ int two_pass_blocks(int nx, int ny);
 // Blocks (one reduction record each) of the fused tile kernel, which takes the
 // lattices the strip kernels do not.
 int tile_blocks(int nx, int ny);
-// Whether the step runs the aligned 64-column strip kernel (fast path on a
-// width that is a multiple of 64), and the strip/segment counts of the fused
-// kernels (one reduction record per strip and segment).
-bool aligned_strips(int nx, int fast);
+// Strip and segment counts of the fused strip kernels (one reduction record
+// per strip and segment): aligned, 64-column strips (the last one partial
+// where the width is not a multiple of 64); otherwise 62-column strips.
 void fused_shape(int nx, int ny, int seg_len, bool aligned, int* n_strips, int* n_segs);
 
 template <class S>

@@ -1,8 +1,9 @@
 // HIP kernels of one pseudopotential MRT step for gfx950 (CDNA4, wave64).
 //
 // Step implementations, all on the node arithmetic of lbm_node.h:
-//  * the aligned strip march (lattices whose width is a multiple of 64): a
-//    wavefront owns 64 aligned columns and marches up a run of rows; each row
+//  * the aligned strip march: a wavefront owns 64 aligned columns (the last
+//    strip of a width that is not a multiple of 64 fewer) and marches up a
+//    run of rows; each row
 //    is pulled once, its density and pseudopotential are computed in
 //    registers, the x-neighbours' psi comes through DPP lane shifts and the
 //    y-neighbours' from the rows kept in registers, and the middle row is
@@ -10,7 +11,8 @@
 //    nodes, moving walls) take the same march with bounce-back chosen per link
 //    from a 16-bit link word per node; the nodes beside moving walls are
 //    stepped first by the tile kernel, on the tiles that hold them only;
-//  * the 62-column strip march (double storage, other widths);
+//  * the 62-column strip march (double storage, widths that are not a
+//    multiple of 64, on lattices that sit in the last-level cache);
 //  * the tile kernel (every other lattice): one node per thread, psi of a
 //    32 x 8 tile and its one-node ring in LDS;
 //  * the two-pass kernels: a psi pass writes the pseudopotential field, then
@@ -490,9 +492,10 @@ __device__ inline double tile_psi_links(const StepParams& p, const S* __restrict
 
 // ------------------------------------------------------------------ fused tile kernel
 //
-// The fused step for every lattice the strip kernels do not take (solid
-// masks, moving walls, widths that are not a multiple of 64 with float
-// storage): a block of 32 x 8 threads owns a 32 x 8 tile, one node per
+// The fused step for every lattice the strip kernels do not take (double
+// storage of masked lattices whose width is not a multiple of 64 and that sit
+// in the last-level cache; 64-bit offsets; and masked lattices when asked
+// for): a block of 32 x 8 threads owns a 32 x 8 tile, one node per
 // thread.  Each thread pulls its node (keeping the pulled populations in
 // registers), computes psi and writes it to an LDS tile with a one-node ring;
 // 84 threads also compute psi of the ring's nodes.  After one barrier every
@@ -1072,8 +1075,8 @@ __global__ __launch_bounds__(256) void fast_kernel(StepParams p, const S* __rest
 
 // ------------------------------------------------------------------ aligned strip kernel
 //
-// The fast kernel for lattices whose width is a multiple of 64.  A wavefront
-// owns 64 aligned columns x0 .. x0+63 (every lane a node), so each row of
+// The fast kernel.  A wavefront owns 64 aligned columns x0 .. x0+63 (every
+// lane a node; a partial last strip, below, fewer), so each row of
 // each population is stored as whole aligned 256-byte (FP32) or 512-byte
 // (FP64) lines.  Overlapping 62-column strips store rows that straddle cache
 // lines shared with the neighbouring strip; measured on gfx950, the march
@@ -1119,6 +1122,7 @@ struct AMarch {
   const double* psi_moving;
   unsigned hidx, hlcol;
   bool lockstep;  // every block holds 4 existing strips (they march in lockstep)
+  bool owner;     // the lane's node belongs to this strip (false past a partial last strip's end)
 };
 
 // Reference offsets of one row (float storage): c at the lane's column (m)
@@ -1347,8 +1351,8 @@ __device__ inline void arow_state(const StepParams& p, const AMarch& m, const AS
   node_sums<S>(d, cm, t.drho, t.jx, t.jy);
   bool bad;
   const double ps = psi_of(p, p.rho_ref + t.drho, bad);
-  t.psi = (t.g.real && !solid) ? (moving ? sl.pm : ps) : p.psi_solid;
-  t.bad = t.g.real && !solid && bad;
+  t.psi = (t.g.real && m.c.real && !solid) ? (moving ? sl.pm : ps) : p.psi_solid;
+  t.bad = t.g.real && m.c.real && !solid && bad;
   // the halo column's density in the same arithmetic as its own strip uses
   double hr = halo_sum((double)sl.rh);
   if constexpr (sizeof(S) == 4) hr += ch;
@@ -1386,7 +1390,7 @@ __device__ inline void amarch_row(const AMarch& m, int y, const ASlot<S>& s0, co
   // solid nodes keep their populations; nodes beside moving walls were
   // collided and stored by moving_kernel
   const bool skip = MASKED && ((s0.lk.own() & LINK_SOLID) || (MOVING && (s0.lk.own() & LINK_MOVING)));
-  const bool store = t0.g.real && !skip;
+  const bool store = t0.g.real && m.owner && !skip;
   double Sx, Sy;
   stencil_sums(pE, t1.psi, pW, tm.psi, pNE, pNW, pSW, pSE, Sx, Sy);
   double dw[9];
@@ -1402,7 +1406,7 @@ __device__ inline void amarch_row(const AMarch& m, int y, const ASlot<S>& s0, co
   }
   const __amdgpu_buffer_rsrc_t out = buf_rsrc(m.fo, t0.g.real ? m.bytes : 0u);
   // a lane that does not store: its stores fall outside the buffer
-  const unsigned col = (!MASKED || store) ? m.c.own * (unsigned)sizeof(S) : m.bytes;
+  const unsigned col = store ? m.c.own * (unsigned)sizeof(S) : m.bytes;
 #pragma unroll
   for (int i = 0; i < 9; ++i)
     BufIO<S>::store(store_value<S>(d[i], wgt(i), (double)cd[i]), out, col,
@@ -1535,8 +1539,15 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
   m.f = f;
   m.fo = fo;
   const int x0 = strip * WAVE;
-  const bool hl = lane == 0 || lane == WAVE - 1;
-  m.c = col_geo(p, x0 + lane, true);
+  // A partial last strip (widths that are not a multiple of 64): its lane w
+  // takes the column after the lattice's last one (wrapped, or beyond the
+  // wall), whose psi the last column needs, and the lanes past it idle;
+  // neither stores.  Such a strip has no column beside it on the right.
+  const int w = min(WAVE, p.nx - x0);
+  const bool ragged = w < WAVE;
+  const bool hl = lane == 0 || (lane == WAVE - 1 && !ragged);
+  m.c = col_geo(p, x0 + min(lane, w), lane <= w);
+  m.owner = lane < w;
   m.h = col_geo(p, lane == 0 ? x0 - 1 : x0 + WAVE, hl);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
@@ -1545,7 +1556,7 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
   }
   {
     // the columns beside the strip, one population per lane
-    const bool left = lane <= 8, right = lane >= 48 && lane <= 56;
+    const bool left = lane <= 8, right = !ragged && lane >= 48 && lane <= 56;
     const int hi = left ? lane : (right ? lane - 48 : 0);
     const ColGeo hg = col_geo(p, left ? x0 - 1 : x0 + WAVE, left || right);
     const int exi = ex(hi);
@@ -1558,7 +1569,7 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
     m.hidx = (unsigned)hi;
     // link word of the column beside the strip: the pulling lanes' column,
     // and lane 63's (which takes that column's psi); the lane's own elsewhere
-    const ColGeo hr = col_geo(p, x0 + WAVE, true);
+    const ColGeo hr = col_geo(p, x0 + WAVE, !ragged);
     m.hlcol = (m.hon ? hg.own : ((lane == WAVE - 1 && hr.real) ? hr.own : m.c.own));
   }
   // float storage: byte offset within a row's reference run of the halo
@@ -1668,10 +1679,8 @@ static dim3 node_grid(const StepParams& p, dim3 blk) {
 
 int two_pass_blocks(int nx, int ny) { return ((nx + 63) / 64) * ((ny + 3) / 4); }
 
-bool aligned_strips(int nx, int fast) { return fast && nx % WAVE == 0; }
-
 void fused_shape(int nx, int ny, int seg_len, bool aligned, int* n_strips, int* n_segs) {
-  *n_strips = aligned ? nx / WAVE : (nx + STRIP - 1) / STRIP;
+  *n_strips = aligned ? (nx + WAVE - 1) / WAVE : (nx + STRIP - 1) / STRIP;
   *n_segs = (ny + seg_len - 1) / seg_len;
 }
 
@@ -1713,7 +1722,7 @@ hipError_t launch_step(const StepParams& p, const StepLaunch& L, hipStream_t st)
   const S* f = (const S*)L.f_in;
   S* fo = (S*)L.f_out;
   // only the aligned strip kernel writes the trajectory
-  if (L.traj && !(L.kernel == 0 && aligned_strips(p.nx, L.fast) && !L.masked)) return hipErrorNotSupported;
+  if (L.traj && !(L.kernel == 0 && L.aligned && !L.masked)) return hipErrorNotSupported;
   if (L.kernel == 1) {
     dim3 blk(64, 4);
     dim3 grd = node_grid(p, blk);
@@ -1724,7 +1733,7 @@ hipError_t launch_step(const StepParams& p, const StepLaunch& L, hipStream_t st)
     else
       hipLaunchKernelGGL((collide_kernel<S, false>), grd, blk, 0, st, p, f, fo, L.mask, L.wall_u,
                          (const double*)L.psi, L.partials);
-  } else if (aligned_strips(p.nx, L.fast) || L.masked) {
+  } else if (L.aligned || L.masked) {
     int n_strips, n_segs;
     fused_shape(p.nx, p.ny, L.seg_len, true, &n_strips, &n_segs);
     int groups = (n_strips + 3) / 4;
@@ -1735,7 +1744,7 @@ hipError_t launch_step(const StepParams& p, const StepLaunch& L, hipStream_t st)
     const dim3 grd(8 * per_xcd), blk(256);
     if (L.traj && L.reduce) return hipErrorInvalidValue;
     if (L.masked) {
-      if (L.traj || p.nx % WAVE != 0 || !L.links) return hipErrorInvalidValue;
+      if (L.traj || !L.links) return hipErrorInvalidValue;
       double* pm = nullptr;
       if (L.wall_u) {
         // the nodes beside moving walls first, on the tile kernel (their reduction
@@ -1774,7 +1783,7 @@ hipError_t launch_step(const StepParams& p, const StepLaunch& L, hipStream_t st)
       hipLaunchKernelGGL((aligned_kernel<S, false, false, false, false>), grd, blk, 0, st, p, f, fo, n_strips, L.seg_len,
                          n_segs, groups, per_xcd, il, L.partials, nullptr, nullptr, nullptr, L.lockstep);
   } else if (L.fast && launch_fast62<S>(p, L, st)) {
-    // launched: the 62-column strip kernel (double storage, widths not a multiple of 64)
+    // launched: the 62-column strip kernel (double storage, widths not a multiple of 64, cache-resident)
   } else {
     dim3 blk(TILE_X, TILE_Y);
     dim3 grd((p.nx + TILE_X - 1) / TILE_X, (p.ny + TILE_Y - 1) / TILE_Y);

@@ -228,8 +228,9 @@ class Lattice:
         self._check(lib().lbm_set_rows_per_wave(self.h, rows), self.h)
 
     def set_masked_strips(self, on: bool):
-        """Masked lattices of width a multiple of 64: the masked strip march (True,
-        default) or the tile kernel (False)."""
+        """Masked lattices: the masked strip march (True, default; double storage of
+        widths that are not a multiple of 64 only on lattices that stream from HBM)
+        or the tile kernel (False)."""
         self._check(lib().lbm_set_masked_strips(self.h, 1 if on else 0), self.h)
 
     # ------------------------------------------------------------ state

@@ -1,5 +1,6 @@
-"""The masked strip march (lattices with solid masks or moving walls whose width
-is a multiple of 64) against the tile kernel, through the C-ABI.
+"""The masked strip march (lattices with solid masks or moving walls) against the
+tile kernel, through the C-ABI; and the strip march over widths that are not a
+multiple of 64, whose last strip is partial.
 
 Both run the same node arithmetic; what differs is the data movement
 (bounce-back chosen from per-node link words, psi of neighbours through lane
@@ -82,8 +83,21 @@ def channel_wall_u(nx=64, ny=40):
     return Masked(w, None, np.zeros((2, ny, nx)))
 
 
+def annulus_ragged():
+    # width 150: two full strips and one of 22 columns (float storage takes the
+    # masked march at any width)
+    w = WL.annular_shear()
+    return w.with_size(150, 150, init_args={"centre": (74.5, 74.5), "r_in": 20.0, "r_out": 70.0, "u_wall": 0.01,
+                                            "r_liq_in": 35.0, "r_liq_out": 55.0})
+
+
 CASES = [
     ("oblique", lambda: WL.poiseuille_oblique(), 30),
+    ("annulus_ragged_150", annulus_ragged, 40),
+    ("blobs_ragged_periodic_x", lambda: droplet_blobs(nx=150, ny=96, seed=7), 40),
+    ("blobs_ragged_walled_moving", lambda: droplet_blobs(nx=100, ny=70, periodic_x=False, periodic_y=False,
+                                                         moving=True, seed=8), 40),
+    ("blobs_one_partial_strip", lambda: droplet_blobs(nx=40, ny=48, periodic_x=True, periodic_y=True, seed=9), 40),
     ("annulus", annulus_aligned, 40),
     ("blobs_periodic_x", lambda: droplet_blobs(), 40),
     ("blobs_walled_x", lambda: droplet_blobs(periodic_x=False, periodic_y=True, seed=2), 40),
@@ -187,3 +201,36 @@ def test_static_workspace_handles_share_it_with_masks(precision):
     for i in range(2):
         assert torch.equal(shared[i].state(), own[i].state()), ws[i].name
         assert recs_s[i] == recs_o[i]
+
+
+def hbm_ragged(mask):
+    # 2000 x 1100 (31 full strips and one of 16 columns), x walls, y periodic:
+    # its two double-storage arrays (317 MB) exceed the last-level cache, so
+    # double storage also takes the strip march with a partial last strip
+    w = WL.small_droplet(nx=2000, ny=1100, radius=120.0, g=1e-5)
+    return Masked(w, mask, None)
+
+
+@pytest.mark.parametrize("precision", [LT.FP64, LT.FP32_DEV])
+def test_partial_last_strip_at_a_size_that_streams_from_hbm(precision):
+    """The unmasked strip march, the masked strip march (a mask with a few solid
+    blobs) and the tile kernel on the same 2000-column lattice: masked march and
+    tile kernel agree as in the masked cases; the unmasked march agrees with the
+    tile kernel on the same lattice with an all-fluid mask."""
+    w0 = hbm_ragged(None)
+    steps = 12
+    print(f"[masked] partial last strip 2000x1100 precision={precision}", flush=True)
+    free = np.zeros((w0.ny, w0.nx), np.uint8)
+    a = LT.Lattice.from_workload(w0, precision=precision)                      # unmasked strip march
+    b = LT.Lattice.from_workload(hbm_ragged(free), precision=precision)        # all-fluid mask, tile kernel
+    b.set_masked_strips(False)
+    m = blobs(w0.nx, w0.ny, 11)
+    m[:, :2] = 0
+    c = LT.Lattice.from_workload(hbm_ragged(m), precision=precision)           # masked strip march
+    d = LT.Lattice.from_workload(hbm_ragged(m), precision=precision)           # masked, tile kernel
+    d.set_masked_strips(False)
+    for lat in (a, b, c, d):
+        lat.step(steps)
+    torch.cuda.synchronize()
+    compare_states(hbm_ragged(free), a, b, precision)
+    compare_states(hbm_ragged(m), c, d, precision)
