@@ -307,8 +307,11 @@ __device__ inline const StepParams& kernarg_params() {
 // source x - e_i is solid or lies beyond a wall (the population then comes
 // from the node's own opposite one); bit 9 moving walls are given and some
 // pull source is a solid node inside the box (the node takes the moving-wall
-// term).  Written from the mask and the periodicity.
-constexpr unsigned LINK_SOLID = 1u, LINK_MOVING = 1u << 9;
+// term).  Written from the mask and the periodicity.  Bit 10 is never stored:
+// the march sets it in registers on the lanes of a partial last strip past
+// the lattice's last column (they store nothing), with bit 0 where that
+// lane's column does not exist.
+constexpr unsigned LINK_SOLID = 1u, LINK_MOVING = 1u << 9, LINK_NOTOWN = 1u << 10;
 
 __global__ __launch_bounds__(256) void links_kernel(StepParams p, const uint8_t* __restrict__ mask, int moving,
                                                    uint16_t* __restrict__ links, unsigned* __restrict__ tile_flags) {
@@ -1121,6 +1124,9 @@ struct AMarch {
   const uint16_t* links;
   const double* psi_moving;
   unsigned hidx, hlcol;
+  // bits ORed into the lane's link word: 0, or on a partial strip's lanes past
+  // the last column LINK_NOTOWN (and LINK_SOLID where the column does not exist)
+  unsigned lkor;
   bool lockstep;  // every block holds 4 existing strips (they march in lockstep)
   bool owner;     // the lane's node belongs to this strip (false past a partial last strip's end)
 };
@@ -1165,6 +1171,7 @@ struct ARow {
 
 // Link words of row y (masked lattices); rows beyond a non-periodic edge read
 // row 0 (they are not pulled).
+template <bool RAGGED>
 __device__ inline LinkPair aload_links(const StepParams& p, const AMarch& m, int y) {
   const RowGeo g = row_geo(p, y);
   const unsigned row = g.real ? g.own : 0u;
@@ -1172,7 +1179,7 @@ __device__ inline LinkPair aload_links(const StepParams& p, const AMarch& m, int
   const unsigned own = (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, (int)(m.c.own * 2u), (int)(row * 2u), 0);
   const unsigned halo = (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, (int)(m.hlcol * 2u), (int)(row * 2u), 0);
   LinkPair lk;
-  lk.w = own | (halo << 16);
+  lk.w = (RAGGED ? (own | m.lkor) : own) | (halo << 16);
   return lk;
 }
 
@@ -1328,7 +1335,7 @@ __device__ inline double halo_sum(double v) {
 // Density, momentum and psi of a pulled row.  Masked lattices: psi_solid on
 // solid nodes; a node beside a moving wall (and a column beside the strip
 // whose node is one) takes the psi moving_kernel computed for it.
-template <class S, bool MASKED, bool MOVING>
+template <class S, bool MASKED, bool MOVING, bool RAGGED>
 __device__ inline void arow_state(const StepParams& p, const AMarch& m, const ASlot<S>& sl, ARow& t) {
   double d[9];
 #pragma unroll
@@ -1351,8 +1358,12 @@ __device__ inline void arow_state(const StepParams& p, const AMarch& m, const AS
   node_sums<S>(d, cm, t.drho, t.jx, t.jy);
   bool bad;
   const double ps = psi_of(p, p.rho_ref + t.drho, bad);
-  t.psi = (t.g.real && m.c.real && !solid) ? (moving ? sl.pm : ps) : p.psi_solid;
-  t.bad = t.g.real && m.c.real && !solid && bad;
+  // a partial strip: the lanes past the lattice's last column that are not
+  // a wrapped column take psi_solid (masked lattices: their link words say
+  // solid)
+  const bool here = t.g.real && (!RAGGED || MASKED || m.c.real);
+  t.psi = (here && !solid) ? (moving ? sl.pm : ps) : p.psi_solid;
+  t.bad = here && !solid && bad;
   // the halo column's density in the same arithmetic as its own strip uses
   double hr = halo_sum((double)sl.rh);
   if constexpr (sizeof(S) == 4) hr += ch;
@@ -1367,7 +1378,7 @@ __device__ inline void arow_state(const StepParams& p, const AMarch& m, const AS
 // and y+1 (`t1`, finished here from slot `s1`); the loads of row y + AHEAD
 // go into slot `sn` first.  Masked lattices: `ln` holds the link words of row
 // y + AHEAD, and the link words of row y + AHEAD + 1 are loaded into `l0`.
-template <class S, bool REDUCE, bool TRAJ, bool INTERIOR, bool MASKED, bool MOVING, int AHEAD>
+template <class S, bool REDUCE, bool TRAJ, bool INTERIOR, bool MASKED, bool MOVING, bool RAGGED, int AHEAD>
 __device__ inline void amarch_row(const AMarch& m, int y, const ASlot<S>& s0, const ASlot<S>& s1, ASlot<S>& sn,
                                   const ARow& tm, const ARow& t0, ARow& t1, ARow& tn, LinkPair& l0,
                                   const LinkPair& ln, double* acc) {
@@ -1376,9 +1387,9 @@ __device__ inline void amarch_row(const AMarch& m, int y, const ASlot<S>& s0, co
   // together, so that the block's loads of a row are one contiguous stretch
   // of each run of that row; a bare barrier, no wait for memory
   if (m.lockstep) __builtin_amdgcn_s_barrier();
-  if (MASKED) l0 = aload_links(p, m, y + AHEAD + 1);
+  if (MASKED) l0 = aload_links<RAGGED>(p, m, y + AHEAD + 1);
   aissue_row<S, INTERIOR, MASKED, MOVING>(p, m, y + AHEAD, y + AHEAD <= m.y1, sn, tn.g, ln);
-  arow_state<S, MASKED, MOVING>(p, m, s1, t1);
+  arow_state<S, MASKED, MOVING, RAGGED>(p, m, s1, t1);
   const double pW = t0.pw, pE = t0.pe;
   const double pSW = tm.pw, pSE = tm.pe;
   const double pNW = t1.pw, pNE = t1.pe;
@@ -1389,8 +1400,8 @@ __device__ inline void amarch_row(const AMarch& m, int y, const ASlot<S>& s0, co
   if constexpr (sizeof(S) == 4) cm = (double)t0.cr.m;
   // solid nodes keep their populations; nodes beside moving walls were
   // collided and stored by moving_kernel
-  const bool skip = MASKED && ((s0.lk.own() & LINK_SOLID) || (MOVING && (s0.lk.own() & LINK_MOVING)));
-  const bool store = t0.g.real && m.owner && !skip;
+  const bool skip = MASKED && ((s0.lk.own() & (LINK_SOLID | LINK_NOTOWN)) || (MOVING && (s0.lk.own() & LINK_MOVING)));
+  const bool store = t0.g.real && (!RAGGED || MASKED || m.owner) && !skip;
   double Sx, Sy;
   stencil_sums(pE, t1.psi, pW, tm.psi, pNE, pNW, pSW, pSE, Sx, Sy);
   double dw[9];
@@ -1406,7 +1417,7 @@ __device__ inline void amarch_row(const AMarch& m, int y, const ASlot<S>& s0, co
   }
   const __amdgpu_buffer_rsrc_t out = buf_rsrc(m.fo, t0.g.real ? m.bytes : 0u);
   // a lane that does not store: its stores fall outside the buffer
-  const unsigned col = store ? m.c.own * (unsigned)sizeof(S) : m.bytes;
+  const unsigned col = ((!MASKED && !RAGGED) || store) ? m.c.own * (unsigned)sizeof(S) : m.bytes;
 #pragma unroll
   for (int i = 0; i < 9; ++i)
     BufIO<S>::store(store_value<S>(d[i], wgt(i), (double)cd[i]), out, col,
@@ -1450,30 +1461,30 @@ __device__ inline void amarch_row(const AMarch& m, int y, const ASlot<S>& s0, co
 // the same or slower for both storages once runs are short.)  Masked
 // lattices keep the link words one row further ahead, so that the offsets of
 // a row's pulls never wait for its link words.
-template <class S, bool REDUCE, bool TRAJ, bool INTERIOR, bool MASKED, bool MOVING>
+template <class S, bool REDUCE, bool TRAJ, bool INTERIOR, bool MASKED, bool MOVING, bool RAGGED>
 __device__ inline void amarch(const StepParams& p, const AMarch& m, int y0, double* acc) {
   ASlot<S> sa, sb, sc;
   ARow ta, tb, tc;
   // link words of the next row each slot receives (masked lattices)
   LinkPair la{0u}, lb{0u}, lc{0u};
   if (MASKED) {
-    lc = aload_links(p, m, y0 - 1);
-    la = aload_links(p, m, y0);
-    lb = aload_links(p, m, y0 + 1);
+    lc = aload_links<RAGGED>(p, m, y0 - 1);
+    la = aload_links<RAGGED>(p, m, y0);
+    lb = aload_links<RAGGED>(p, m, y0 + 1);
   }
   // row r lives in slot (r - y0 + 1) mod 3: y0-1 -> c, y0 -> a, y0+1 -> b
   aissue_row<S, INTERIOR, MASKED, MOVING>(p, m, y0 - 1, true, sc, tc.g, lc);
   aissue_row<S, INTERIOR, MASKED, MOVING>(p, m, y0, true, sa, ta.g, la);
   aissue_row<S, INTERIOR, MASKED, MOVING>(p, m, y0 + 1, true, sb, tb.g, lb);
-  if (MASKED) lc = aload_links(p, m, y0 + 2);
-  arow_state<S, MASKED, MOVING>(p, m, sc, tc);
-  arow_state<S, MASKED, MOVING>(p, m, sa, ta);
+  if (MASKED) lc = aload_links<RAGGED>(p, m, y0 + 2);
+  arow_state<S, MASKED, MOVING, RAGGED>(p, m, sc, tc);
+  arow_state<S, MASKED, MOVING, RAGGED>(p, m, sa, ta);
   for (int y = y0; y < m.y1; y += 3) {
-    amarch_row<S, REDUCE, TRAJ, INTERIOR, MASKED, MOVING, 2>(m, y, sa, sb, sc, tc, ta, tb, tc, la, lc, acc);
+    amarch_row<S, REDUCE, TRAJ, INTERIOR, MASKED, MOVING, RAGGED, 2>(m, y, sa, sb, sc, tc, ta, tb, tc, la, lc, acc);
     if (y + 1 >= m.y1) break;
-    amarch_row<S, REDUCE, TRAJ, INTERIOR, MASKED, MOVING, 2>(m, y + 1, sb, sc, sa, ta, tb, tc, ta, lb, la, acc);
+    amarch_row<S, REDUCE, TRAJ, INTERIOR, MASKED, MOVING, RAGGED, 2>(m, y + 1, sb, sc, sa, ta, tb, tc, ta, lb, la, acc);
     if (y + 2 >= m.y1) break;
-    amarch_row<S, REDUCE, TRAJ, INTERIOR, MASKED, MOVING, 2>(m, y + 2, sc, sa, sb, tb, tc, ta, tb, lc, lb, acc);
+    amarch_row<S, REDUCE, TRAJ, INTERIOR, MASKED, MOVING, RAGGED, 2>(m, y + 2, sc, sa, sb, tb, tc, ta, tb, lc, lb, acc);
   }
 }
 
@@ -1546,8 +1557,15 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
   const int w = min(WAVE, p.nx - x0);
   const bool ragged = w < WAVE;
   const bool hl = lane == 0 || (lane == WAVE - 1 && !ragged);
-  m.c = col_geo(p, x0 + min(lane, w), lane <= w);
-  m.owner = lane < w;
+  m.owner = true;
+  m.lkor = 0u;
+  if (!ragged) {
+    m.c = col_geo(p, x0 + lane, true);
+  } else {
+    m.c = col_geo(p, x0 + min(lane, w), lane <= w);
+    m.owner = lane < w;
+    m.lkor = lane < w ? 0u : (LINK_NOTOWN | (m.c.real ? 0u : LINK_SOLID));
+  }
   m.h = col_geo(p, lane == 0 ? x0 - 1 : x0 + WAVE, hl);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
@@ -1596,12 +1614,20 @@ __global__ __launch_bounds__(256) void aligned_kernel(StepParams p, const S* __r
   // Interior strips (the pulls of columns x0-1 .. x0+64 stay inside the box
   // without wrapping) of y-periodic lattices take the select-free offsets.
   const bool interior = p.periodic_y && x0 >= 2 && x0 + WAVE + 1 <= p.nx - 1;
-  if (MASKED)
-    amarch<S, REDUCE, TRAJ, false, true, MOVING>(p, m, y0, acc);
+  // (a partial strip of an unmasked lattice, at most one per run, takes its
+  // own instance of the march, so that whole strips keep theirs unchanged;
+  // the masked march marks the lanes past the last column in their link
+  // words instead)
+  if (MASKED && ragged)
+    amarch<S, REDUCE, TRAJ, false, true, MOVING, true>(p, m, y0, acc);
+  else if (MASKED)
+    amarch<S, REDUCE, TRAJ, false, true, MOVING, false>(p, m, y0, acc);
   else if (interior)
-    amarch<S, REDUCE, TRAJ, true, false, false>(p, m, y0, acc);
+    amarch<S, REDUCE, TRAJ, true, false, false, false>(p, m, y0, acc);
+  else if (ragged)
+    amarch<S, REDUCE, TRAJ, false, false, false, true>(p, m, y0, acc);
   else
-    amarch<S, REDUCE, TRAJ, false, false, false>(p, m, y0, acc);
+    amarch<S, REDUCE, TRAJ, false, false, false, false>(p, m, y0, acc);
 
   if (REDUCE) {
 #pragma unroll
