@@ -332,7 +332,9 @@ def accuracy_run(w, total, every, reref):
 def masked_workloads(steps, warmup, min_warmup_s):
     """MLUPS of the masked workloads (solid masks; moving walls on the annulus) on
     the masked strip march, the default, and beside it on the tile kernel.  These
-    lattices fit in the 256 MB last-level cache, so they are not HBM-bound."""
+    lattices fit in the 256 MB last-level cache, so they are not HBM-bound.  Also a
+    droplet channel whose width, 2000, is not a multiple of 64 (the strip march
+    with a partial last strip)."""
     from paper_2604_13407_amd import lattice as LT
     from paper_2604_13407_amd import workloads as WL
     others, tiles = {}, {}
@@ -344,6 +346,11 @@ def masked_workloads(steps, warmup, min_warmup_s):
             others[f"{name}_{tag}"] = round(wo.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1)
             r = gpu_run(wo, prec, steps, warmup, 0, min_warmup_s, tile=True)
             tiles[f"{name}_{tag}"] = round(wo.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1)
+    # a width that is not a multiple of 64: 31 strips and a partial one of 16 columns
+    wr = WL.small_droplet(nx=2000, ny=4096, radius=200.0, g=1e-6)
+    for prec, tag in ((LT.FP32_DEV, "fp32"), (LT.FP64, "fp64")):
+        r = gpu_run(wr, prec, steps, warmup, 0, min_warmup_s)
+        others[f"droplet_2000x4096_partial_strip_{tag}"] = round(wr.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1)
     return {"other_workloads_MLUPS": others, "other_workloads_tile_kernel_MLUPS": tiles}
 
 
