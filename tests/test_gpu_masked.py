@@ -166,11 +166,12 @@ def test_masked_march_state_does_not_depend_on_rows_per_wave(precision):
         assert torch.equal(lat.state(), ref.state()), rows
 
 
+@pytest.mark.parametrize("nx", [128, 150])
 @pytest.mark.parametrize("precision", [LT.FP64, LT.FP32_DEV])
-def test_masked_march_rereference_and_resume(precision):
+def test_masked_march_rereference_and_resume(precision, nx):
     # float storage re-references with the mask; a resumed run is bitwise the
-    # uninterrupted one
-    w = droplet_blobs(moving=True, periodic_y=True, seed=5)
+    # uninterrupted one (also with a partial last strip)
+    w = droplet_blobs(nx=nx, moving=True, periodic_y=True, seed=5)
     a = LT.Lattice.from_workload(w, precision=precision)
     a.set_rereference_every(7)
     a.step(20)
