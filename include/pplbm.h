@@ -202,7 +202,12 @@ int lbm_init_equilibrium(lbm_lattice* h, const double* rho0_dev, const double* u
  * cfg.log_capacity per call, else LBM_ERR_INVALID_ARG before any work).  If
  * out_host is non-NULL, min(records, n_out) records are copied to it and the
  * stream is synchronised; a record with faults > 0 then makes the call return
- * LBM_ERR_EOS_DOMAIN or LBM_ERR_NONFINITE after the copy. */
+ * LBM_ERR_EOS_DOMAIN or LBM_ERR_NONFINITE after the copy.  With out_host NULL
+ * the call only enqueues kernels on the handle's stream (no allocation, copy,
+ * memset or synchronisation), so a caller may capture it into a HIP graph; the
+ * handle's step counter (and with it the steps that reduce and re-reference)
+ * advances when the call is made, not when the graph replays, and an even n
+ * leaves the state in the array it started from. */
 int lbm_step(lbm_lattice* h, int64_t n, int32_t reduce_every, lbm_reduction* out_host, int64_t n_out);
 
 /* Launch tuning of the fused strip kernels (unmasked lattices, and masked
