@@ -41,6 +41,25 @@ def build(verbose: bool = True) -> str:
     return LIB
 
 
+C_CLIENT_SRC = os.path.join(ROOT, "tests", "c_client", "lbm_c_client.c")
+C_CLIENT = os.path.join(HERE, "lbm_c_client")
+
+
+def build_c_client(verbose: bool = True) -> str:
+    """The plain-C client of the library (tests/c_client): gcc, C99, linked
+    against liblbm.so beside it and the HIP runtime."""
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+    cmd = ["gcc", "-std=c99", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+           "-I", os.path.join(rocm, "include"), C_CLIENT_SRC, "-o", C_CLIENT + ".tmp", "-L", HERE, "-llbm",
+           "-L", os.path.join(rocm, "lib"), "-lamdhip64", "-lm", "-Wl,-rpath,$ORIGIN",
+           "-Wl,-rpath," + os.path.join(rocm, "lib")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(C_CLIENT + ".tmp", C_CLIENT)
+    return C_CLIENT
+
+
 def stale() -> bool:
     if not os.path.exists(LIB):
         return True
@@ -50,4 +69,5 @@ def stale() -> bool:
 
 if __name__ == "__main__":
     build()
+    build_c_client()
     sys.exit(0)
