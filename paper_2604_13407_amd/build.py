@@ -48,7 +48,7 @@ C_CLIENT = os.path.join(HERE, "lbm_c_client")
 def build_c_client(verbose: bool = True) -> str:
     """The plain-C client of the library (tests/c_client): gcc, C99, linked
     against liblbm.so beside it and the HIP runtime."""
-    rocm = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+    rocm = os.path.realpath(os.environ.get("ROCM_PATH", "/opt/rocm"))
     cmd = ["gcc", "-std=c99", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
            "-I", os.path.join(rocm, "include"), C_CLIENT_SRC, "-o", C_CLIENT + ".tmp", "-L", HERE, "-llbm",
            "-L", os.path.join(rocm, "lib"), "-lamdhip64", "-lm", "-Wl,-rpath,$ORIGIN",
