@@ -31,13 +31,16 @@ def annulus_aligned():
 
 
 def blobs(nx, ny, seed, frac=0.08):
-    """A seeded mask of solid blobs (and isolated solid nodes)."""
+    """A seeded mask of solid blobs (and isolated solid nodes).  Each blob is
+    drawn in its bounding box (the same mask as testing every node)."""
     rng = np.random.default_rng(seed)
     m = np.zeros((ny, nx), np.uint8)
-    yy, xx = np.mgrid[0:ny, 0:nx]
     for _ in range(max(1, int(frac * nx * ny / 30))):
         cx, cy, r = rng.uniform(0, nx), rng.uniform(0, ny), rng.uniform(1.0, 4.0)
-        m[(xx - cx) ** 2 + (yy - cy) ** 2 < r * r] = 1
+        x0, x1 = max(0, int(cx - r) - 1), min(nx, int(cx + r) + 2)
+        y0, y1 = max(0, int(cy - r) - 1), min(ny, int(cy + r) + 2)
+        yy, xx = np.mgrid[y0:y1, x0:x1]
+        m[y0:y1, x0:x1][(xx - cx) ** 2 + (yy - cy) ** 2 < r * r] = 1
     m[rng.random((ny, nx)) < 0.01] = 1
     return m
 
