@@ -51,6 +51,12 @@ def test_sizes_and_config_validation():
         assert L.lbm_last_error(None).decode(), bad
         assert L.lbm_workspace_bytes(C.byref(cfg(**bad)), C.byref(b)) == -1, bad
         assert L.lbm_last_error(None).decode(), bad
+    # the largest lattice accepted (9 nx ny < 2^31) and one row more
+    big = dict(nx=16384, ny=14563, precision=LT.FP64)
+    assert L.lbm_state_bytes(C.byref(cfg(**big)), C.byref(b)) == 0 and b.value == 9 * 8 * 16384 * 14563
+    assert L.lbm_workspace_bytes(C.byref(cfg(**big)), C.byref(b)) == 0
+    assert L.lbm_state_bytes(C.byref(cfg(**dict(big, ny=14564))), C.byref(b)) == -1
+    assert "2^31" in L.lbm_last_error(None).decode()
     assert L.lbm_workspace_bytes(C.byref(cfg()), None) == -1
     assert "NULL" in L.lbm_last_error(None).decode()
     # and a successful one clears it
