@@ -188,7 +188,7 @@ def test_autograd_function_chains_the_adjoint():
                     checkpoint_every=K_SMALL)
     (3.0 * L).backward()
     Lr, gG, gf, g, _ = gpu_gradients(w, mask, kind, ut, N_SMALL, W_SMALL, K_SMALL)
-    assert float(L) == Lr
+    assert float(L.detach()) == Lr
     assert float(f.grad) == 3.0 * gf and float(G.grad) == 3.0 * gG
     assert np.array_equal(rho0.grad.cpu().numpy(), 3.0 * g)
 
